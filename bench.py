@@ -1,0 +1,310 @@
+"""Benchmark: RK3 cell-substeps/s and HBM roofline fraction of the 512^3 single run
+(FP64, with FP32 side by side), the batched 48-run ensemble, and a served Poisson
+run stream, on one MI355X.  Prints ONE JSON line.
+
+Timing follows the paper's benchmark protocol (Appendix A): warm-up steps, then
+timed steps, per-step time reported with its 90th percentile next to the mean.
+Every input is synthetic and seeded (see mhd_inputs).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import mhd_inputs as mi  # noqa: E402
+
+METRIC = "RK3 cell-substeps/s + HBM GB/s at 512^3; ensemble steps/s and p99 step latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per cell over one RK3 step (two-buffer 2N form):
+# substep 1 reads 7 and writes 7 values, substeps 2 and 3 read 14 and write 7
+VALUES_PER_CELL_STEP = 14 + 21 + 21
+# the paper's figure for this workload (512^3 FP64, 4x V100): 0.65 ns per point-step
+PAPER_NS_PER_POINT_STEP = 0.65
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else 0.0
+
+
+def single_run(mhd, n, prec, warmup, steps, nu=4e-4):
+    """512^3 non-helical forced run from the Section 4 initial condition."""
+    p = mhd.make_params(n, nu=nu, eta=nu, dt=1e-3, precision=prec)
+    h = mhd.mhd_create(p)
+    try:
+        mhd.mhd_init_seed(h, 0, 1e-5)
+        mhd.mhd_set_forcing_random(h, 3.0, 0.02, 0.0, 0)
+        mhd.mhd_step(h, warmup)
+        mhd.mhd_sync(h)
+        kms, step_ms = mhd.mhd_step_timed(h, steps)
+        diag = mhd.mhd_get_diag(h)
+        tile = mhd.mhd_tile_config(p)
+    finally:
+        mhd.mhd_destroy(h)
+    cells = float(n) ** 3
+    ms = float(np.mean(step_ms))
+    rate = 3.0 * cells / (ms * 1e-3)
+    bytes_step = VALUES_PER_CELL_STEP * prec * cells
+    sub_ms = kms[0] + kms[1] + kms[2]
+    achieved = bytes_step / (sub_ms * 1e-3) / 1e9
+    return dict(
+        cell_substeps_per_s=rate, ms_per_step=ms, p50_ms=pct(step_ms, 50), p90_ms=pct(step_ms, 90),
+        p99_ms=pct(step_ms, 99), hbm_gbs=bytes_step / (ms * 1e-3) / 1e9,
+        kernel_ms=dict(substep1=kms[0], substep2=kms[1], substep3=kms[2], finalize=kms[3]),
+        substep_kernel_gbs=achieved, tile=tile, nonfinite=max(d["nonfinite"] for d in diag),
+        ns_per_point_step=ms * 1e6 / cells)
+
+
+def cpu_baseline(n=512, nz=64, seed=0):
+    """The oracle, as it stands, on a bounded sample of the 512^3 workload: one full RK3
+    step of an n x n x nz periodic box (same per-cell work), all host cores."""
+    import oracle
+    rp = mi.RunParams(n, n, nz, nu=4e-4, eta=4e-4, dt=1e-3)
+    st = mi.ic_seed_noise(rp, seed, 1e-5)
+    rec = mi.forcing_schedule(seed, 1, 3.0, 0.02, 0.0)
+    threads = oracle.get_threads()
+    t0 = time.perf_counter()
+    oracle.step(st, rp, rec)
+    dt = time.perf_counter() - t0
+    cells = float(n * n * nz)
+    return dict(value=3.0 * cells / dt, unit="cell-substeps/s", cores=threads, kind="oracle",
+                sample=f"one RK3 step of the FP64 oracle on a {n}x{n}x{nz} periodic box "
+                       f"(same per-cell work as 512^3; {dt:.1f} s)",
+                seconds=dt, cpu=_cpu_model())
+
+
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def ensemble(mhd, nsteps=500, alone_steps=None):
+    """48 runs (32 x 64^3 + 16 x 128^3), FP32, advanced together in graph-captured
+    launches; compared with the same runs advanced one by one by the plain solver."""
+    import torch
+    runs = mi.ensemble_runs()
+    params = [mhd.make_params(r["n"], nu=r["nu"], eta=r["eta"], dt=r["dt"], precision=r["precision"])
+              for r in runs]
+    b = mhd.mhd_batch_create(params)
+    try:
+        ctxs = [mhd.mhd_batch_ctx(b, i) for i in range(len(runs))]
+        for c, r in zip(ctxs, runs):
+            mhd.mhd_init_seed(c, r["seed"], r["a_noise"])
+            mhd.mhd_set_forcing_random(c, r["kf"], r["f0"], r["sigma"], r["seed"])
+        mhd.mhd_batch_run(b, 2, True)       # capture + warm-up
+        for c in ctxs:
+            mhd.mhd_sync(c)
+        t0 = time.perf_counter()
+        mhd.mhd_batch_run(b, nsteps, True)
+        mhd.mhd_sync(ctxs[0])
+        wall = time.perf_counter() - t0
+        # per-ensemble-step latency: eager launches, one sync per step
+        lat = []
+        for _ in range(50):
+            ta = time.perf_counter()
+            mhd.mhd_batch_run(b, 1, False)
+            mhd.mhd_sync(ctxs[0])
+            lat.append((time.perf_counter() - ta) * 1e3)
+        bad = sum(mhd.mhd_get_diag(c)[-1]["nonfinite"] > 0 for c in ctxs)
+    finally:
+        mhd.mhd_batch_destroy(b)
+    cells = sum(float(r["n"]) ** 3 for r in runs)
+    # the same runs one at a time through the single-run path
+    alone_steps = alone_steps or nsteps
+    t_alone = 0.0
+    alone_lat = []
+    for r, p in zip(runs, params):
+        h = mhd.mhd_create(p)
+        try:
+            mhd.mhd_init_seed(h, r["seed"], r["a_noise"])
+            mhd.mhd_set_forcing_random(h, r["kf"], r["f0"], r["sigma"], r["seed"])
+            mhd.mhd_step(h, 2)
+            mhd.mhd_sync(h)
+            ta = time.perf_counter()
+            mhd.mhd_step(h, alone_steps)
+            mhd.mhd_sync(h)
+            el = time.perf_counter() - ta
+            t_alone += el * nsteps / alone_steps
+            alone_lat.append(el * 1e3 / alone_steps)
+        finally:
+            mhd.mhd_destroy(h)
+    del torch
+    return dict(runs=len(runs), steps=nsteps, wall_s=wall,
+                ensemble_steps_per_s=len(runs) * nsteps / wall,
+                cell_substeps_per_s=3.0 * cells * nsteps / wall,
+                effective_gbs=VALUES_PER_CELL_STEP * 4 * cells * nsteps / wall / 1e9,
+                step_latency_p50_ms=pct(lat, 50), step_latency_p99_ms=pct(lat, 99),
+                alone_wall_s=t_alone, alone_ensemble_steps_per_s=len(runs) * nsteps / t_alone,
+                speedup_vs_alone=t_alone / wall, nonfinite_runs=int(bad))
+
+
+def serving(mhd, nruns=40, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tick=5):
+    """First `nruns` arrivals of the Poisson trace (rate 4/s, N in {32,64,128,256}, FP32,
+    `nsteps` steps each), served with continuous batching; the FCFS one-at-a-time
+    baseline uses measured standalone service times on the same arrivals."""
+    trace = mi.serving_trace(240, nsteps=nsteps)[:nruns]
+    srv = mhd.mhd_server_create(int(budget_gb * 2 ** 30), slots, steps_per_tick)
+    ids = []
+    try:
+        mhd.mhd_server_start(srv)
+        t0 = time.perf_counter()
+        for r in trace:
+            while time.perf_counter() - t0 < r["arrival"]:
+                time.sleep(0.001)
+            p = mhd.make_params(r["n"], nu=r["nu"], eta=r["eta"], dt=r["dt"], precision=r["precision"])
+            ids.append(mhd.mhd_server_submit(srv, p, r["seed"], r["a_noise"], r["kf"], r["f0"],
+                                             r["sigma"], r["nsteps"]))
+        for rid in ids:
+            mhd.mhd_server_wait(srv, rid, 600.0)
+        makespan = time.perf_counter() - t0
+        st = mhd.mhd_server_stats_get(srv)
+    finally:
+        mhd.mhd_server_destroy(srv)
+    # baseline: each distinct run size alone, then FCFS over the same arrivals
+    service = {}
+    step_ms = {}
+    for n in sorted({r["n"] for r in trace}):
+        p = mhd.make_params(n, nu=1e-3, eta=1e-3, dt=1e-3, precision=4)
+        h = mhd.mhd_create(p)
+        try:
+            mhd.mhd_init_seed(h, 0, 1e-5)
+            mhd.mhd_set_forcing_random(h, 3.0, 0.02, 0.0, 0)
+            mhd.mhd_step(h, 5)
+            mhd.mhd_sync(h)
+            m = min(nsteps, 200)
+            ta = time.perf_counter()
+            mhd.mhd_step(h, m)
+            mhd.mhd_sync(h)
+            step_ms[n] = (time.perf_counter() - ta) * 1e3 / m
+            service[n] = step_ms[n] * nsteps / 1e3
+        finally:
+            mhd.mhd_destroy(h)
+    free_at, fin, lat = 0.0, [], []
+    for r in trace:
+        start = max(free_at, r["arrival"])
+        free_at = start + service[r["n"]]
+        fin.append(free_at - r["arrival"])
+        lat.extend([step_ms[r["n"]]] * 1)
+    fcfs_makespan = free_at
+    return dict(runs=nruns, steps_per_run=nsteps, makespan_s=makespan,
+                runs_per_hour=nruns / makespan * 3600.0,
+                step_latency_p50_ms=st.lat_p50_ms, step_latency_p99_ms=st.lat_p99_ms,
+                queue_p50_s=st.queue_p50_s, queue_p99_s=st.queue_p99_s,
+                e2e_p50_s=st.e2e_p50_s, e2e_p99_s=st.e2e_p99_s,
+                completed=int(st.completed), failed=int(st.failed),
+                hbm_peak_gb=st.hbm_peak / 2 ** 30, cell_substeps_per_s=st.cell_substeps / max(st.busy_s, 1e-9),
+                fcfs_alone=dict(makespan_s=fcfs_makespan, runs_per_hour=nruns / fcfs_makespan * 3600.0,
+                                e2e_p50_s=pct(fin, 50), e2e_p99_s=pct(fin, 99),
+                                step_latency_ms={str(k): v for k, v in step_ms.items()}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-runs", type=int, default=40)
+    ap.add_argument("--ensemble-steps", type=int, default=500)
+    ap.add_argument("--cpu-nz", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU slab decomposition is design-only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    import paper_2012_08758_amd as mhd
+
+    log(f"[bench] {args.n}^3 FP64: {args.warmup} warm-up + {args.steps} timed steps")
+    r64 = single_run(mhd, args.n, mhd.MHD_FP64, args.warmup, args.steps)
+    log(f"[bench] FP64 {r64['cell_substeps_per_s']:.3e} cell-substeps/s, {r64['ms_per_step']:.2f} ms/step")
+    r32 = None
+    if not args.no_fp32:
+        log(f"[bench] {args.n}^3 FP32")
+        r32 = single_run(mhd, args.n, mhd.MHD_FP32, args.warmup, args.steps)
+        log(f"[bench] FP32 {r32['cell_substeps_per_s']:.3e} cell-substeps/s, {r32['ms_per_step']:.2f} ms/step")
+    ens = None
+    if not args.no_ensemble:
+        log("[bench] ensemble: 48 runs x %d steps" % args.ensemble_steps)
+        ens = ensemble(mhd, args.ensemble_steps)
+        log(f"[bench] ensemble {ens['ensemble_steps_per_s']:.1f} run-steps/s, x{ens['speedup_vs_alone']:.2f} vs alone")
+    srv = None
+    if not args.no_serve:
+        log(f"[bench] serving: {args.serve_runs} Poisson arrivals")
+        srv = serving(mhd, args.serve_runs)
+        log(f"[bench] serving {srv['runs_per_hour']:.0f} runs/h, p99 step {srv['step_latency_p99_ms']:.2f} ms")
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle sample")
+        cpu = cpu_baseline(args.n, args.cpu_nz)
+        log(f"[bench] oracle {cpu['value']:.3e} cell-substeps/s on {cpu['cores']} threads")
+
+    cells = float(args.n) ** 3
+    achieved = r64["substep_kernel_gbs"]
+    out = {
+        "metric": METRIC,
+        "value": r64["cell_substeps_per_s"],
+        "unit": "cell-substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": r64["cell_substeps_per_s"] / (3.0 / (PAPER_NS_PER_POINT_STEP * 1e-9)),
+        "baseline_note": "paper: 0.65 ns per point-step, 512^3 FP64 on 4x V100 (other hardware; context)",
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.n}^3 single run, FP64 (FP32 beside), non-helical forcing kf=3, "
+                               "f0=0.02, nu=eta=4e-4, dt=1e-3, A noise 1e-5",
+                   "grid": [args.n] * 3, "tile": r64["tile"]},
+        "hbm_gbs": r64["hbm_gbs"],
+        "p50_ms_per_step": r64["p50_ms"],
+        "p90_ms_per_step": r64["p90_ms"],
+        "p99_ms_per_step": r64["p99_ms"],
+        "ns_per_point_step": r64["ns_per_point_step"],
+        "kernel_ms": r64["kernel_ms"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_substep (fused RHS + RK3 substep)",
+                     "bytes_per_cell_substep": VALUES_PER_CELL_STEP * 8 / 3.0},
+        "cpu_baseline": cpu,
+        "fp32": None if r32 is None else {
+            "value": r32["cell_substeps_per_s"], "ms_per_step": r32["ms_per_step"],
+            "p90_ms_per_step": r32["p90_ms"], "hbm_gbs": r32["hbm_gbs"],
+            "substep_kernel_gbs": r32["substep_kernel_gbs"],
+            "roofline_frac": r32["substep_kernel_gbs"] / HBM_PEAK_GBS, "kernel_ms": r32["kernel_ms"],
+            "tile": r32["tile"]},
+        "ensemble": ens,
+        "serving": srv,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

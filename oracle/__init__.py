@@ -62,6 +62,8 @@ def lib():
         L.ora_step.argtypes = [dp, C.POINTER(_Params), C.POINTER(_Forcing), C.c_int64, dp]
         L.ora_step_cells.argtypes = [dp, C.POINTER(_Params), C.POINTER(_Forcing), C.c_int64,
                                      C.POINTER(C.c_int64), dp]
+        L.ora_terms_cells.argtypes = [dp, C.POINTER(_Params), C.POINTER(_Forcing), C.c_int64,
+                                      C.POINTER(C.c_int64), dp]
         L.ora_rhs_patch.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                     C.POINTER(_Params), C.POINTER(_Forcing), dp]
         L.ora_deriv.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -140,6 +142,16 @@ def step_cells(state, p, rec, cells):
                               cl.ctypes.data_as(C.POINTER(C.c_int64)), _dp(out))
     if rc != 0:
         raise MemoryError("oracle step_cells: allocation failed")
+    return out
+
+
+def terms_cells(state, p, rec, cells):
+    """(ncells, 7, 7): |term| per cell, field and term of the right-hand side at ``state``."""
+    st = _state64(state, p)
+    cl = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.zeros((len(cl), 7, 7))
+    lib().ora_terms_cells(_dp(st), C.byref(_params(p)), _forcings([rec]), len(cl),
+                          cl.ctypes.data_as(C.POINTER(C.c_int64)), _dp(out))
     return out
 
 

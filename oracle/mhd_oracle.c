@@ -405,6 +405,22 @@ int ora_step_cells(const double *state, const ora_params *p, const ora_forcing *
     return fail ? -1 : 0;
 }
 
+/* |term| of every RHS term at the listed cells of the periodic state (the scale
+ * that roundoff of one step is measured against).  out: ncells*7*NTERM. */
+int ora_terms_cells(const double *state, const ora_params *p, const ora_forcing *fr,
+                    int64_t ncells, const int64_t *cells, double *out)
+{
+    view v = full_view(state, p);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < ncells; q++) {
+        int64_t c = cells[q];
+        int i = (int)(c % p->nx), j = (int)((c / p->nx) % p->ny), l = (int)(c / ((int64_t)p->nx * p->ny));
+        double r[NF];
+        rhs_cell(&v, p, fr, i, j, l, r, out + q * NF * NTERM);
+    }
+    return 0;
+}
+
 /* Right-hand side on a non-periodic patch of size (mx, my, mz) whose local
  * (0,0,0) is global index (ox, oy, oz); only cells at least 3 from every face are
  * evaluated (the others are set to NaN).  Grid spacing comes from p. */

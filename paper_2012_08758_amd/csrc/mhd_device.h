@@ -1,0 +1,505 @@
+// Device-side data structures and kernels of the MHD solver (gfx950).
+//
+// One launch = one RK3 substep of every run in a tile list.  Each work-group owns a
+// TX x TY x TZ box of cells of one run.  The seven fields pass through a
+// double-buffered LDS tile one at a time (box + 3-cell halo, periodic indices
+// wrapped while staging); while field f is differentiated out of one buffer, field
+// f+1 streams from HBM into the other.  Every right-hand-side term is folded into
+// per-cell accumulators as soon as the field it needs has passed, so registers
+// hold ~23 values per cell instead of ~60 derivatives.  The RK3 update is fused:
+// the output of substep s overwrites, cell by cell, the buffer holding substep s-2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mhd {
+
+// Pointers that the kernels dereference are cast to the global address space, so
+// loads and stores are global_* (vector-memory counter only) instead of flat_*
+// (which also occupy the LDS counter and serialise against LDS reads).
+template <typename T>
+using G = __attribute__((address_space(1))) T;
+
+constexpr int NF = 7;
+constexpr int DIAGW = 10;  // per-tile partials: |B|^2, |u|^2, rho|u|^2, lnrho, Bx, By, Bz, max|u|^2, nonfinite, spare
+constexpr int DREC = 12;   // record: step, t, em, ek, urms, brms, umax, <lnrho>, <Bx>, <By>, <Bz>, nonfinite
+constexpr int FHEAD = 8;   // forcing block head: a[3], b[3], on, spare
+
+template <typename T>
+struct Coef {
+    T d1[3][3];   // first derivative: weight of offset m+1, divided by h_axis
+    T d2[3][4];   // second derivative: weight of offset m (m = 0 centre), divided by h_axis^2
+    T dm[3][3];   // mixed derivative, pair 0 = xy, 1 = xz, 2 = yz: weight of diagonal offset m+1 / (4 h_a h_b)
+    T cs2, nu, nu3, nu2_3, eta;
+    T bext[3];
+    T bdt[3];     // beta_s * dt
+    T brho[3];    // beta_s * alpha_s / beta_{s-1} (0 for s = 0)
+};
+
+struct DCoef {      // FP64 copy of the curl weights, for diagnostics of FP32 runs
+    double d1[3][3];
+    double bext[3];
+};
+
+template <typename T>
+struct RunDesc {
+    T *buf[2][NF];
+    int nx, ny, nz, parity0;
+    int first_tile, ntiles, fstride, pad;
+    Coef<T> c;
+    DCoef dc;
+    const T *forcing;   // per batch step: FHEAD values then Ex[2nx], Ey[2ny], Ez[2nz]
+    double *partials;   // [ntiles][DIAGW]
+    double *records;    // [batch step][DREC]
+    double step0;       // global step index of batch step 0
+    double t0, dt;
+};
+
+struct TileEnt {
+    int run;
+    int xy;    // x0 | (y0 << 16)
+    int z0;
+    int tir;   // tile index within its run (partials slot)
+};
+
+template <typename T>
+__device__ __forceinline__ T sd1(const T *s, int st, const T *w)
+{
+    return w[0] * (s[st] - s[-st]) + w[1] * (s[2 * st] - s[-2 * st]) + w[2] * (s[3 * st] - s[-3 * st]);
+}
+
+template <typename T>
+__device__ __forceinline__ T sd2(const T *s, int st, const T *w)
+{
+    return w[0] * s[0] + w[1] * (s[st] + s[-st]) + w[2] * (s[2 * st] + s[-2 * st]) +
+           w[3] * (s[3 * st] + s[-3 * st]);
+}
+
+// d_a d_b from the (a+b) and (a-b) diagonals
+template <typename T>
+__device__ __forceinline__ T sdm(const T *s, int sa, int sb, const T *w)
+{
+    const int p = sa + sb, q = sa - sb;
+    return w[0] * ((s[p] + s[-p]) - (s[q] + s[-q])) +
+           w[1] * ((s[2 * p] + s[-2 * p]) - (s[2 * q] + s[-2 * q])) +
+           w[2] * ((s[3 * p] + s[-3 * p]) - (s[3 * q] + s[-3 * q]));
+}
+
+__device__ __forceinline__ double sd1d(const float *s, int st, const double *w)
+{
+    return w[0] * ((double)s[st] - (double)s[-st]) + w[1] * ((double)s[2 * st] - (double)s[-2 * st]) +
+           w[2] * ((double)s[3 * st] - (double)s[-3 * st]);
+}
+__device__ __forceinline__ double sd1d(const double *s, int st, const double *w)
+{
+    return w[0] * (s[st] - s[-st]) + w[1] * (s[2 * st] - s[-2 * st]) + w[2] * (s[3 * st] - s[-3 * st]);
+}
+
+__device__ __forceinline__ bool finite_v(float v) { return __builtin_isfinite(v); }
+__device__ __forceinline__ bool finite_v(double v) { return __builtin_isfinite(v); }
+
+__device__ __forceinline__ int wrapi(int v, int n)
+{
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Per-cell accumulators of one thread (CZ cells along z).
+template <typename T, int CZ>
+struct Cells {
+    T v[CZ][NF];        // centre values
+    T g[CZ][3];         // grad ln rho
+    T B[CZ][3], J[CZ][3];
+    T R[CZ][NF];        // right-hand side accumulators
+    double Bd[CZ][3];   // FP64 curl, for the diagnostics
+};
+
+template <int A, int SY, int SZ>
+struct Stride {
+    static constexpr int v = A == 0 ? 1 : (A == 1 ? SY : SZ);
+};
+
+// index of the mixed pair {a, b}: xy -> 0, xz -> 1, yz -> 2
+template <int A, int B>
+struct Pair {
+    static constexpr int v = (A + B == 1) ? 0 : ((A + B == 2) ? 1 : 2);
+};
+
+// Pin the accumulators in registers at this point of the program.  Without it the
+// optimiser sinks each pass's arithmetic to the final update and keeps the raw LDS
+// reads of every pass alive (and spilled) until then.
+template <typename T, int CZ>
+__device__ __forceinline__ void pin(Cells<T, CZ> &C)
+{
+#pragma unroll
+    for (int c = 0; c < CZ; c++) {
+#pragma unroll
+        for (int f = 0; f < NF; f++) asm volatile("" : "+v"(C.R[c][f]), "+v"(C.v[c][f]));
+#pragma unroll
+        for (int a = 0; a < 3; a++) asm volatile("" : "+v"(C.g[c][a]), "+v"(C.B[c][a]), "+v"(C.J[c][a]), "+v"(C.Bd[c][a]));
+    }
+}
+
+// Fold the derivatives of field F at this thread's cells into the accumulators.
+// Fields pass in the order ln rho, A_x, A_y, A_z, u_x, u_y, u_z.
+template <typename T, int F, int SY, int SZ, int CZ, bool DIAG>
+__device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&cidx)[CZ], const Coef<T> &K,
+                                       const DCoef &dc)
+{
+    constexpr bool IS_F64 = sizeof(T) == 8;
+    constexpr int s0 = 1, s1 = SY, s2 = SZ;
+#pragma unroll
+    for (int c = 0; c < CZ; c++) {
+        const T *s = S + cidx[c];
+        if constexpr (F == 0) {
+            C.g[c][0] = sd1(s, s0, K.d1[0]);
+            C.g[c][1] = sd1(s, s1, K.d1[1]);
+            C.g[c][2] = sd1(s, s2, K.d1[2]);
+            C.R[c][0] -= C.v[c][1] * C.g[c][0] + C.v[c][2] * C.g[c][1] + C.v[c][3] * C.g[c][2];
+            C.R[c][1] -= K.cs2 * C.g[c][0];
+            C.R[c][2] -= K.cs2 * C.g[c][1];
+            C.R[c][3] -= K.cs2 * C.g[c][2];
+        } else if constexpr (F >= 4) {
+            constexpr int m = F - 4;  // A_m
+            constexpr int b1 = (m + 1) % 3, b2 = (m + 2) % 3;  // the other two axes, cyclic
+            constexpr int st1 = Stride<b1, SY, SZ>::v, st2 = Stride<b2, SY, SZ>::v, stm = Stride<m, SY, SZ>::v;
+            C.v[c][F] = s[0];
+            const T d2m = sd2(s, stm, K.d2[m]);
+            const T d21 = sd2(s, st1, K.d2[b1]);
+            const T d22 = sd2(s, st2, K.d2[b2]);
+            C.R[c][F] += K.eta * (d2m + d21 + d22);
+            // j_m = sum_{b != m} (d_m d_b A_b - d_b d_b A_m): the second part here
+            C.J[c][m] -= d21 + d22;
+            // j_b += d_b d_m A_m for b != m
+            C.J[c][b1] += sdm(s, st1, stm, K.dm[Pair<b1, m>::v]);
+            C.J[c][b2] += sdm(s, st2, stm, K.dm[Pair<b2, m>::v]);
+            // B = curl A: A_m enters B_{b1} with + d_{b2} A_m and B_{b2} with - d_{b1} A_m
+            const T e1 = sd1(s, st1, K.d1[b1]);
+            const T e2 = sd1(s, st2, K.d1[b2]);
+            C.B[c][b1] += e2;
+            C.B[c][b2] -= e1;
+            if constexpr (DIAG) {
+                if constexpr (IS_F64) {
+                    C.Bd[c][b1] += (double)e2;
+                    C.Bd[c][b2] -= (double)e1;
+                } else {
+                    C.Bd[c][b1] += sd1d(s, st2, dc.d1[b2]);
+                    C.Bd[c][b2] -= sd1d(s, st1, dc.d1[b1]);
+                }
+            }
+            if constexpr (F == 6) {
+                // A complete: Lorentz force and induction
+                C.B[c][0] += K.bext[0];
+                C.B[c][1] += K.bext[1];
+                C.B[c][2] += K.bext[2];
+                const T rinv = exp(-C.v[c][0]);
+                const T *Bv = C.B[c], *Jv = C.J[c], *u = &C.v[c][1];
+                C.R[c][1] += rinv * (Jv[1] * Bv[2] - Jv[2] * Bv[1]);
+                C.R[c][2] += rinv * (Jv[2] * Bv[0] - Jv[0] * Bv[2]);
+                C.R[c][3] += rinv * (Jv[0] * Bv[1] - Jv[1] * Bv[0]);
+                C.R[c][4] += u[1] * Bv[2] - u[2] * Bv[1];
+                C.R[c][5] += u[2] * Bv[0] - u[0] * Bv[2];
+                C.R[c][6] += u[0] * Bv[1] - u[1] * Bv[0];
+            }
+        } else {
+            constexpr int m = F - 1;  // u_m
+            constexpr int b1 = (m + 1) % 3, b2 = (m + 2) % 3;
+            constexpr int st1 = Stride<b1, SY, SZ>::v, st2 = Stride<b2, SY, SZ>::v, stm = Stride<m, SY, SZ>::v;
+            T du[3];
+            du[m] = sd1(s, stm, K.d1[m]);
+            du[b1] = sd1(s, st1, K.d1[b1]);
+            du[b2] = sd1(s, st2, K.d1[b2]);
+            const T d2m = sd2(s, stm, K.d2[m]);
+            const T lap = d2m + sd2(s, st1, K.d2[b1]) + sd2(s, st2, K.d2[b2]);
+            const T *g = C.g[c], *u = &C.v[c][1];
+            // viscous: nu lap u_m + nu/3 d_m d_m u_m; advection; strain row m
+            T rm = K.nu * lap + K.nu3 * d2m;
+            rm -= u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+            rm += K.nu * (du[0] * g[0] + du[1] * g[1] + du[2] * g[2]);
+            C.R[c][1 + m] += rm;
+            C.R[c][0] -= du[m];
+            // strain column m and trace part, for every component a
+#pragma unroll
+            for (int a = 0; a < 3; a++) C.R[c][1 + a] += K.nu * du[a] * g[m] - K.nu2_3 * du[m] * g[a];
+            // grad div u: d_a d_m u_m for a != m
+            C.R[c][1 + b1] += K.nu3 * sdm(s, st1, stm, K.dm[Pair<b1, m>::v]);
+            C.R[c][1 + b2] += K.nu3 * sdm(s, st2, stm, K.dm[Pair<b2, m>::v]);
+        }
+    }
+    pin(C);
+}
+
+template <typename T, int NL, int NT, int VOL>
+__device__ __forceinline__ void stage_load(T (&stage)[NL], const G<T> *src, const uint32_t (&gofs)[NL])
+{
+#pragma unroll
+    for (int k = 0; k < NL; k++) stage[k] = src[gofs[k]];
+}
+
+template <typename T, int NL, int NT, int VOL>
+__device__ __forceinline__ void stage_store(T *dst, const T (&stage)[NL], int tid)
+{
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+        const int q = tid + k * NT;
+        if (k < NL - 1 || q < VOL) dst[q] = stage[k];
+    }
+}
+
+template <typename T, int TX, int TY, int TZ, int CZ, int SUB, bool DIAG, bool STORE, int WPE>
+__global__ void __launch_bounds__(TX * TY * (TZ / CZ), WPE)
+k_substep(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
+{
+    constexpr int NT = TX * TY * (TZ / CZ);
+    constexpr int XW = TX + 6, YW = TY + 6, ZW = TZ + 6;
+    constexpr int VOL = XW * YW * ZW;
+    constexpr int NL = (VOL + NT - 1) / NT;
+    constexpr int SY = XW, SZ = XW * YW;
+    constexpr int ZS = TZ / CZ;  // z distance between a thread's cells
+
+    __shared__ __align__(16) T lds[2][VOL];
+
+    const TileEnt te = tiles[blockIdx.x];
+    const RunDesc<T> &r = runs[te.run];
+    const int nx = r.nx, ny = r.ny, nz = r.nz;
+    const int x0 = te.xy & 0xffff, y0 = te.xy >> 16, z0 = te.z0;
+    const int par = (r.parity0 + step) & 1;
+    // substep 0 and the diagnostic pass read X, substep 1 reads Y, substep 2 reads X
+    const int in_set = (SUB == 1) ? (par ^ 1) : par;
+    const int out_set = (SUB == 1) ? par : (par ^ 1);
+    const G<T> *in[NF];
+    G<T> *out[NF];
+#pragma unroll
+    for (int f = 0; f < NF; f++) {
+        in[f] = (const G<T> *)r.buf[in_set][f];
+        out[f] = (G<T> *)r.buf[out_set][f];
+    }
+
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz0 = tid / (TX * TY);
+
+    // global offsets of this thread's share of the halo box (same for every field)
+    uint32_t gofs[NL];
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+        int q = tid + k * NT;
+        if (q >= VOL) q = VOL - 1;
+        const int qx = q % XW, qy = (q / XW) % YW, qz = q / SZ;
+        const int gx = wrapi(x0 - 3 + qx, nx), gy = wrapi(y0 - 3 + qy, ny), gz = wrapi(z0 - 3 + qz, nz);
+        gofs[k] = (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz);
+    }
+
+    // this thread's cells
+    int cidx[CZ];
+    uint32_t gcell[CZ];
+    bool inside[CZ];
+#pragma unroll
+    for (int c = 0; c < CZ; c++) {
+        const int lz = lz0 + c * ZS;
+        cidx[c] = (lz + 3) * SZ + (ly + 3) * SY + (lx + 3);
+        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        inside[c] = gx < nx && gy < ny && gz < nz;
+        gcell[c] = inside[c] ? (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz) : 0u;
+    }
+
+    Cells<T, CZ> C;
+#pragma unroll
+    for (int c = 0; c < CZ; c++) {
+#pragma unroll
+        for (int f = 0; f < NF; f++) C.R[c][f] = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; a++) { C.B[c][a] = T(0); C.J[c][a] = T(0); C.Bd[c][a] = 0.0; }
+        // u and ln rho at the cell are needed by every pass: read them first
+        C.v[c][0] = in[0][gcell[c]];
+        C.v[c][1] = in[1][gcell[c]];
+        C.v[c][2] = in[2][gcell[c]];
+        C.v[c][3] = in[3][gcell[c]];
+    }
+
+    const Coef<T> &K = r.c;
+    const DCoef &dc = r.dc;
+    T stage[NL];
+
+    stage_load<T, NL, NT, VOL>(stage, in[0], gofs);
+    stage_store<T, NL, NT, VOL>(lds[0], stage, tid);
+    __syncthreads();
+    // Each pass: issue the next field's loads, differentiate the current field out
+    // of LDS, then write the staged values.  The scheduling fences keep the compiler
+    // from hoisting the LDS writes (and their wait on the loads) above the compute.
+    stage_load<T, NL, NT, VOL>(stage, in[4], gofs);
+    __builtin_amdgcn_sched_barrier(0);
+    absorb<T, 0, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+    __builtin_amdgcn_sched_barrier(0);
+    stage_store<T, NL, NT, VOL>(lds[1], stage, tid);
+    __syncthreads();
+    stage_load<T, NL, NT, VOL>(stage, in[5], gofs);
+    __builtin_amdgcn_sched_barrier(0);
+    absorb<T, 4, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
+    __builtin_amdgcn_sched_barrier(0);
+    stage_store<T, NL, NT, VOL>(lds[0], stage, tid);
+    __syncthreads();
+    stage_load<T, NL, NT, VOL>(stage, in[6], gofs);
+    __builtin_amdgcn_sched_barrier(0);
+    absorb<T, 5, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+    __builtin_amdgcn_sched_barrier(0);
+    stage_store<T, NL, NT, VOL>(lds[1], stage, tid);
+    __syncthreads();
+    stage_load<T, NL, NT, VOL>(stage, in[1], gofs);
+    __builtin_amdgcn_sched_barrier(0);
+    absorb<T, 6, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
+    __builtin_amdgcn_sched_barrier(0);
+    stage_store<T, NL, NT, VOL>(lds[0], stage, tid);
+    __syncthreads();
+    if constexpr (STORE) {
+        stage_load<T, NL, NT, VOL>(stage, in[2], gofs);
+        __builtin_amdgcn_sched_barrier(0);
+        absorb<T, 1, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+        __builtin_amdgcn_sched_barrier(0);
+        stage_store<T, NL, NT, VOL>(lds[1], stage, tid);
+        __syncthreads();
+        stage_load<T, NL, NT, VOL>(stage, in[3], gofs);
+        __builtin_amdgcn_sched_barrier(0);
+        absorb<T, 2, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
+        __builtin_amdgcn_sched_barrier(0);
+        stage_store<T, NL, NT, VOL>(lds[0], stage, tid);
+        __syncthreads();
+        absorb<T, 3, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+
+        // forcing (held fixed over the step's substeps)
+        const G<T> *fs = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
+        if (fs[6] != T(0)) {
+            const G<T> *Ex = fs + FHEAD, *Ey = Ex + 2 * nx, *Ez = Ey + 2 * ny;
+#pragma unroll
+            for (int c = 0; c < CZ; c++) {
+                if (!inside[c]) continue;
+                const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz0 + c * ZS;
+                const T xr = Ex[2 * gx], xi = Ex[2 * gx + 1];
+                const T yr = Ey[2 * gy], yi = Ey[2 * gy + 1];
+                const T zr = Ez[2 * gz], zi = Ez[2 * gz + 1];
+                const T pr = xr * yr - xi * yi, pi = xr * yi + xi * yr;
+                const T cr = pr * zr - pi * zi, ci = pr * zi + pi * zr;
+#pragma unroll
+                for (int a = 0; a < 3; a++) C.R[c][1 + a] += fs[a] * cr + fs[3 + a] * ci;
+            }
+        }
+
+        const T bdt = K.bdt[SUB], brho = K.brho[SUB];
+#pragma unroll
+        for (int c = 0; c < CZ; c++) {
+            if (!inside[c]) continue;
+#pragma unroll
+            for (int f = 0; f < NF; f++) {
+                T o;
+                if constexpr (SUB == 0) {
+                    o = C.v[c][f] + bdt * C.R[c][f];
+                } else {
+                    const T old = out[f][gcell[c]];
+                    o = C.v[c][f] + brho * (C.v[c][f] - old) + bdt * C.R[c][f];
+                }
+                out[f][gcell[c]] = o;
+            }
+        }
+    }
+
+    if constexpr (DIAG) {
+        // the diagnostic-only pass still needs the A centre values for its finiteness check
+        double acc[9];
+#pragma unroll
+        for (int q = 0; q < 9; q++) acc[q] = 0.0;
+#pragma unroll
+        for (int c = 0; c < CZ; c++) {
+            if (!inside[c]) continue;
+            const double bx = C.Bd[c][0] + dc.bext[0], by = C.Bd[c][1] + dc.bext[1], bz = C.Bd[c][2] + dc.bext[2];
+            const double ux = (double)C.v[c][1], uy = (double)C.v[c][2], uz = (double)C.v[c][3];
+            const double u2 = ux * ux + uy * uy + uz * uz;
+            const double b2 = bx * bx + by * by + bz * bz;
+            acc[0] += b2;
+            acc[1] += u2;
+            acc[2] += exp((double)C.v[c][0]) * u2;
+            acc[3] += (double)C.v[c][0];
+            acc[4] += bx;
+            acc[5] += by;
+            acc[6] += bz;
+            acc[7] = fmax(acc[7], u2);
+            bool ok = true;
+#pragma unroll
+            for (int f = 0; f < NF; f++) ok = ok && finite_v(C.v[c][f]);
+            acc[8] += ok ? 0.0 : 1.0;
+        }
+        // wave reduction, then across waves through LDS (fixed order: deterministic)
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double w = __shfl_xor(acc[q], o, 64);
+                acc[q] = (q == 7) ? fmax(acc[q], w) : acc[q] + w;
+            }
+        }
+        constexpr int NW = NT / 64;
+        __syncthreads();
+        double *red = reinterpret_cast<double *>(&lds[1][0]);
+        const int wave = tid / 64, lane = tid % 64;
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 9; q++) red[wave * 9 + q] = acc[q];
+        }
+        __syncthreads();
+        if (tid < 9) {
+            double s = red[tid];
+            for (int w = 1; w < NW; w++) s = (tid == 7) ? fmax(s, red[w * 9 + tid]) : s + red[w * 9 + tid];
+            ((G<double> *)r.partials)[(size_t)te.tir * DIAGW + tid] = s;
+        }
+    }
+}
+
+// Per-run reduction of the tile partials into one diagnostic record (one block per
+// run, 256 threads, compensated sums in a fixed order).
+template <typename T>
+__global__ void __launch_bounds__(256) k_finalize(const RunDesc<T> *__restrict__ runs, int step)
+{
+    const RunDesc<T> &r = runs[blockIdx.x];
+    __shared__ double sh[256][10];
+    const int t = threadIdx.x;
+    double s[9], cmp[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) { s[q] = 0.0; cmp[q] = 0.0; }
+    for (int i = t; i < r.ntiles; i += 256) {
+        const double *p = r.partials + (size_t)i * DIAGW;
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            const double x = p[q];
+            if (q == 7) { s[q] = fmax(s[q], x); continue; }
+            const double u = s[q] + x;
+            cmp[q] += (fabs(s[q]) >= fabs(x)) ? ((s[q] - u) + x) : ((x - u) + s[q]);
+            s[q] = u;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; q++) sh[t][q] = (q == 7) ? s[q] : s[q] + cmp[q];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int q = 0; q < 9; q++) sh[t][q] = (q == 7) ? fmax(sh[t][q], sh[t + w][q]) : sh[t][q] + sh[t + w][q];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double n = (double)r.nx * (double)r.ny * (double)r.nz;
+        double *o = r.records + (size_t)step * DREC;
+        o[0] = r.step0 + (double)step;
+        o[1] = r.t0 + (double)step * r.dt;
+        o[2] = 0.5 * sh[0][0] / n;
+        o[3] = 0.5 * sh[0][2] / n;
+        o[4] = sqrt(sh[0][1] / n);
+        o[5] = sqrt(sh[0][0] / n);
+        o[6] = sqrt(sh[0][7]);
+        o[7] = sh[0][3] / n;
+        o[8] = sh[0][4] / n;
+        o[9] = sh[0][5] / n;
+        o[10] = sh[0][6] / n;
+        o[11] = sh[0][8];
+    }
+}
+
+}  // namespace mhd

@@ -1,0 +1,92 @@
+// Host-side internals shared by the C ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mhd.h"
+#include "mhd_device.h"
+
+namespace mhd {
+
+struct Shape {
+    int tx, ty, tz, cz;
+};
+constexpr int NSHAPES = 6;
+extern const Shape SHAPES[NSHAPES];
+
+// steps whose forcing blocks and diagnostic records are staged at once
+constexpr int CHUNK = 256;
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+mhd_status fail(mhd_status s, const std::string &msg);
+extern thread_local std::string g_err;
+
+}  // namespace mhd
+
+struct mhd_ctx {
+    mhd_params p{};
+    size_t ncell = 0;
+    hipStream_t stream = nullptr;
+    int shape = 0;
+    int ntiles = 0;
+    int fstride = 0;
+    bool owns = false;
+    bool in_batch = false;
+    void *mem = nullptr;
+    void *bufs[2][mhd::NF] = {};
+    int parity = 0;          // buffer set holding the current state
+    int64_t step = 0;        // global step index of the current state
+    // forcing: 0 none, 1 explicit schedule, 2 random on demand
+    int fmode = 0;
+    std::vector<mhd_forcing> sched;
+    int64_t sched_start = 0;
+    double kf = 0, f0 = 0, sigma = 0;
+    uint64_t fseed = 0;
+    // device scratch: forcing blocks, records, partials, descriptor, tile table
+    void *aux = nullptr;
+    size_t aux_bytes = 0;
+    void *d_forcing = nullptr;
+    double *d_records = nullptr;
+    double *d_partials = nullptr;
+    void *d_desc = nullptr;
+    mhd::TileEnt *d_tiles = nullptr;
+    void *h_stage = nullptr;
+    size_t h_stage_bytes = 0;
+    hipEvent_t stage_evt = nullptr;
+    int64_t rcount = 0;      // records written on the device since the last drain
+    std::vector<mhd_diag> host_diag;
+};
+
+namespace mhd {
+
+mhd_status check_params(const mhd_params *p);
+mhd_status check_forcing(const mhd_forcing &f);
+int default_shape(const mhd_params &p);
+int forcing_stride(const mhd_params &p);
+int run_ntiles(const mhd_params &p, int shape);
+void run_tiles(const mhd_params &p, int shape, int run, std::vector<TileEnt> &out);
+std::vector<TileEnt> xcd_order(const std::vector<TileEnt> &nat);
+size_t ctx_footprint(const mhd_params &p);
+mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *bufs, int shape);
+void ctx_release(mhd_ctx *c);
+mhd_status ctx_step(mhd_ctx *c, int64_t n);
+mhd_status ctx_drain(mhd_ctx *c);
+mhd_status ctx_init_seed(mhd_ctx *c, uint64_t seed, double amp);
+mhd_status ctx_forcing_blocks(mhd_ctx *c, int64_t n0, int64_t m, void *dst);
+mhd_forcing random_forcing(double kf, double f0, double sigma, uint64_t seed, int64_t n);
+
+template <typename T>
+void fill_desc(const mhd_ctx *c, RunDesc<T> &d, int parity0, int64_t step0, const T *forcing, double *records,
+               double *partials, int first_tile);
+template <typename T>
+hipError_t launch_substep(int shape, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles, int step,
+                          hipStream_t st);
+template <typename T>
+hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int step, hipStream_t st);
+
+}  // namespace mhd

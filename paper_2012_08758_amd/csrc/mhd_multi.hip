@@ -1,0 +1,677 @@
+// Many independent runs advanced together: the batched ensemble (mhd_batch_*) and
+// the continuous-batching request loop (mhd_server_*).
+//
+// Runs are grouped by (precision, tile shape).  Each group has one tile list that
+// concatenates the tiles of its runs (XCD-ordered) and one array of run
+// descriptors; a substep of the whole group is one kernel launch.  Every run keeps
+// its own buffers, forcing blocks, partials and records, so its arithmetic is the
+// same cell by cell as when it runs alone.
+#include "mhd.h"
+#include "mhd_host.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+namespace mhd {
+
+struct Group {
+    int prec = 8;
+    int shape = 0;
+    std::vector<mhd_ctx *> members;
+    int ntiles = 0;
+    TileEnt *d_tiles = nullptr;
+    void *d_descs = nullptr;
+    void *h_descs = nullptr;   // pinned staging
+    size_t desc_bytes = 0;
+};
+
+struct MultiRunner {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<Group> groups;
+    hipEvent_t stage_evt = nullptr;
+    // captured graphs, keyed by number of steps
+    std::map<int64_t, hipGraphExec_t> graphs;
+
+    ~MultiRunner() { clear(); }
+
+    void clear_graphs()
+    {
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+        graphs.clear();
+    }
+
+    void clear()
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        clear_graphs();
+        for (auto &g : groups) {
+            if (g.d_tiles) (void)hipFree(g.d_tiles);
+            if (g.d_descs) (void)hipFree(g.d_descs);
+            if (g.h_descs) (void)hipHostFree(g.h_descs);
+        }
+        groups.clear();
+        if (stage_evt) (void)hipEventDestroy(stage_evt);
+        stage_evt = nullptr;
+    }
+
+    mhd_status init_stream(void *s)
+    {
+        if (s) {
+            stream = (hipStream_t)s;
+        } else {
+            // graph capture needs a stream other than the legacy default stream
+            if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
+                return fail(MHD_E_DEVICE, "hipStreamCreate failed");
+            own_stream = true;
+        }
+        return MHD_OK;
+    }
+
+    void destroy_stream()
+    {
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+        own_stream = false;
+    }
+
+    // (Re)build the groups for this set of contexts.
+    mhd_status build(const std::vector<mhd_ctx *> &runs)
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        clear_graphs();
+        for (auto &g : groups) {
+            if (g.d_tiles) (void)hipFree(g.d_tiles);
+            if (g.d_descs) (void)hipFree(g.d_descs);
+            if (g.h_descs) (void)hipHostFree(g.h_descs);
+        }
+        groups.clear();
+        if (!stage_evt && hipEventCreateWithFlags(&stage_evt, hipEventDisableTiming) != hipSuccess)
+            return fail(MHD_E_DEVICE, "hipEventCreate failed");
+        std::map<std::pair<int, int>, size_t> index;
+        for (mhd_ctx *c : runs) {
+            auto key = std::make_pair(c->p.precision, c->shape);
+            auto it = index.find(key);
+            if (it == index.end()) {
+                index[key] = groups.size();
+                Group g;
+                g.prec = c->p.precision;
+                g.shape = c->shape;
+                groups.push_back(g);
+                it = index.find(key);
+            }
+            groups[it->second].members.push_back(c);
+        }
+        for (auto &g : groups) {
+            std::vector<TileEnt> nat;
+            for (size_t i = 0; i < g.members.size(); i++) run_tiles(g.members[i]->p, g.shape, (int)i, nat);
+            std::vector<TileEnt> ord = xcd_order(nat);
+            g.ntiles = (int)ord.size();
+            g.desc_bytes = g.members.size() * (g.prec == MHD_FP64 ? sizeof(RunDesc<double>) : sizeof(RunDesc<float>));
+            if (hipMalloc(&g.d_tiles, ord.size() * sizeof(TileEnt)) != hipSuccess ||
+                hipMalloc(&g.d_descs, g.desc_bytes) != hipSuccess ||
+                hipHostMalloc(&g.h_descs, g.desc_bytes, hipHostMallocDefault) != hipSuccess)
+                return fail(MHD_E_OOM, "batch: allocating tile lists failed");
+            if (hipMemcpy(g.d_tiles, ord.data(), ord.size() * sizeof(TileEnt), hipMemcpyHostToDevice) != hipSuccess)
+                return fail(MHD_E_DEVICE, "batch: tile upload failed");
+        }
+        return MHD_OK;
+    }
+
+    template <typename T>
+    hipError_t launch_group_step(Group &g, int s)
+    {
+        const RunDesc<T> *d = (const RunDesc<T> *)g.d_descs;
+        const int nr = (int)g.members.size();
+        hipError_t e = launch_substep<T>(g.shape, 0, d, g.d_tiles, g.ntiles, s, stream);
+        if (e == hipSuccess) e = launch_finalize<T>(d, nr, s, stream);
+        if (e == hipSuccess) e = launch_substep<T>(g.shape, 1, d, g.d_tiles, g.ntiles, s, stream);
+        if (e == hipSuccess) e = launch_substep<T>(g.shape, 2, d, g.d_tiles, g.ntiles, s, stream);
+        return e;
+    }
+
+    hipError_t launch_steps(int64_t m)
+    {
+        for (int64_t s = 0; s < m; s++)
+            for (auto &g : groups) {
+                hipError_t e = g.prec == MHD_FP64 ? launch_group_step<double>(g, (int)s)
+                                                  : launch_group_step<float>(g, (int)s);
+                if (e != hipSuccess) return e;
+            }
+        return hipSuccess;
+    }
+
+    // Stage forcing blocks and descriptors of every run for m steps, enqueue uploads.
+    mhd_status stage(int64_t m)
+    {
+        if (hipEventSynchronize(stage_evt) != hipSuccess) return fail(MHD_E_DEVICE, "staging event failed");
+        for (auto &g : groups) {
+            for (size_t i = 0; i < g.members.size(); i++) {
+                mhd_ctx *c = g.members[i];
+                if (c->rcount + m > CHUNK) {
+                    mhd_status st = ctx_drain(c);
+                    if (st != MHD_OK) return st;
+                }
+                if (hipEventSynchronize(c->stage_evt) != hipSuccess) return fail(MHD_E_DEVICE, "staging event failed");
+                mhd_status st = ctx_forcing_blocks(c, c->step, m, c->h_stage);
+                if (st != MHD_OK) return st;
+                const size_t fbytes = (size_t)m * c->fstride * c->p.precision;
+                if (hipMemcpyAsync(c->d_forcing, c->h_stage, fbytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+                    hipEventRecord(c->stage_evt, stream) != hipSuccess)
+                    return fail(MHD_E_DEVICE, "forcing upload failed");
+                if (g.prec == MHD_FP64)
+                    fill_desc<double>(c, ((RunDesc<double> *)g.h_descs)[i], c->parity, c->step,
+                                      (const double *)c->d_forcing, c->d_records + (size_t)c->rcount * DREC,
+                                      c->d_partials, 0);
+                else
+                    fill_desc<float>(c, ((RunDesc<float> *)g.h_descs)[i], c->parity, c->step,
+                                     (const float *)c->d_forcing, c->d_records + (size_t)c->rcount * DREC,
+                                     c->d_partials, 0);
+            }
+            if (hipMemcpyAsync(g.d_descs, g.h_descs, g.desc_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+                return fail(MHD_E_DEVICE, "descriptor upload failed");
+        }
+        if (hipEventRecord(stage_evt, stream) != hipSuccess) return fail(MHD_E_DEVICE, "event record failed");
+        return MHD_OK;
+    }
+
+    void advance(int64_t m)
+    {
+        for (auto &g : groups)
+            for (mhd_ctx *c : g.members) {
+                c->rcount += m;
+                c->parity ^= (int)(m & 1);
+                c->step += m;
+            }
+    }
+
+    // Advance every run by nsteps (chunks of at most CHUNK steps).
+    mhd_status run(int64_t nsteps, bool use_graph)
+    {
+        while (nsteps > 0) {
+            const int64_t m = std::min<int64_t>(nsteps, CHUNK);
+            mhd_status st = stage(m);
+            if (st != MHD_OK) return st;
+            if (use_graph) {
+                auto it = graphs.find(m);
+                if (it == graphs.end()) {
+                    hipGraph_t graph;
+                    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                        return fail(MHD_E_DEVICE, "hipStreamBeginCapture failed");
+                    hipError_t e = launch_steps(m);
+                    hipError_t e2 = hipStreamEndCapture(stream, &graph);
+                    if (e != hipSuccess || e2 != hipSuccess)
+                        return fail(MHD_E_DEVICE, std::string("graph capture failed: ") +
+                                                      hipGetErrorString(e != hipSuccess ? e : e2));
+                    hipGraphExec_t exec;
+                    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(graph);
+                    if (e != hipSuccess)
+                        return fail(MHD_E_DEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(e));
+                    it = graphs.emplace(m, exec).first;
+                }
+                if (hipGraphLaunch(it->second, stream) != hipSuccess) return fail(MHD_E_DEVICE, "graph launch failed");
+            } else {
+                hipError_t e = launch_steps(m);
+                if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+            }
+            advance(m);
+            nsteps -= m;
+        }
+        return MHD_OK;
+    }
+};
+
+}  // namespace mhd
+
+using namespace mhd;
+
+struct mhd_batch {
+    std::vector<mhd_ctx *> runs;
+    MultiRunner mr;
+};
+
+// ====================================================================== serving
+
+namespace mhd {
+
+struct Request {
+    int64_t id = 0;
+    mhd_params p{};
+    uint64_t seed = 0;
+    double a_noise = 0, kf = 0, f0 = 0, sigma = 0;
+    int64_t nsteps = 0;
+    bool retain = false;
+    int state = MHD_RUN_QUEUED;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int64_t steps_done = 0;
+    size_t footprint = 0;
+    mhd_ctx *ctx = nullptr;
+    std::vector<std::vector<char>> kept;   // retained final state (host)
+    double em = 0, brms = 0;
+};
+
+static double pct(std::vector<double> v, double q)
+{
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (double)(v.size() - 1);
+    const size_t lo = (size_t)std::floor(pos), hi = std::min(v.size() - 1, lo + 1);
+    return v[lo] + (pos - (double)lo) * (v[hi] - v[lo]);
+}
+
+}  // namespace mhd
+
+struct mhd_server {
+    size_t budget = 0;
+    int max_slots = 0;
+    int steps_per_tick = 1;
+    MultiRunner mr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread worker;
+    std::atomic<bool> running{false};
+    std::atomic<bool> stop_req{false};
+    std::map<int64_t, std::unique_ptr<Request>> reqs;
+    std::deque<int64_t> queue;
+    std::vector<int64_t> active;
+    int64_t next_id = 1;
+    size_t in_use = 0, peak = 0;
+    int64_t n_sub = 0, n_adm = 0, n_done = 0, n_fail = 0, ticks = 0;
+    std::vector<double> step_lat_ms;   // one sample per (run, step)
+    std::vector<double> queue_s, e2e_s;
+    double busy_s = 0, cell_substeps = 0;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double first_submit = -1.0, last_done = 0.0;
+    std::string worker_error;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    void loop();
+};
+
+void mhd_server::loop()
+{
+    bool set_changed = true;
+    std::vector<mhd_ctx *> ctxs;
+    while (!stop_req.load()) {
+        // admission (FIFO) by footprint and free slots
+        std::vector<Request *> admit;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (active.empty() && queue.empty()) {
+                cv.wait_for(lk, std::chrono::milliseconds(5));
+                continue;
+            }
+            while (!queue.empty() && (int)(active.size() + admit.size()) < max_slots) {
+                Request *r = reqs[queue.front()].get();
+                if (in_use + r->footprint > budget) break;
+                in_use += r->footprint;
+                peak = std::max(peak, in_use);
+                queue.pop_front();
+                admit.push_back(r);
+            }
+        }
+        for (Request *r : admit) {
+            mhd_ctx *c = new mhd_ctx();
+            mhd_status st = ctx_init(c, &r->p, mr.stream, nullptr, -1);
+            if (st == MHD_OK) st = ctx_init_seed(c, r->seed, r->a_noise);
+            if (st == MHD_OK) {
+                c->fmode = 2;
+                c->kf = r->kf;
+                c->f0 = r->f0;
+                c->sigma = r->sigma;
+                c->fseed = r->seed;
+                c->in_batch = true;
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            if (st != MHD_OK) {
+                ctx_release(c);
+                delete c;
+                r->state = MHD_RUN_FAILED;
+                r->t_done = now();
+                in_use -= r->footprint;
+                n_fail++;
+                cv.notify_all();
+                continue;
+            }
+            r->ctx = c;
+            r->state = MHD_RUN_ACTIVE;
+            r->t_admit = now();
+            queue_s.push_back(r->t_admit - r->t_submit);
+            active.push_back(r->id);
+            n_adm++;
+            set_changed = true;
+        }
+        std::vector<Request *> act;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (int64_t id : active) act.push_back(reqs[id].get());
+        }
+        if (act.empty()) continue;
+        if (set_changed) {
+            ctxs.clear();
+            for (Request *r : act) ctxs.push_back(r->ctx);
+            if (mr.build(ctxs) != MHD_OK) {
+                worker_error = g_err;
+                break;
+            }
+            set_changed = false;
+        }
+        int64_t k = steps_per_tick;
+        for (Request *r : act) k = std::min<int64_t>(k, r->nsteps - r->steps_done);
+        const double ta = now();
+        mhd_status st = mr.run(k, false);
+        if (st == MHD_OK && hipStreamSynchronize(mr.stream) != hipSuccess) st = fail(MHD_E_DEVICE, "device error in tick");
+        const double tb = now();
+        if (st != MHD_OK) {
+            worker_error = g_err;
+            break;
+        }
+        double cells = 0;
+        for (Request *r : act) cells += (double)r->ctx->ncell;
+        // a run whose state went non-finite is evicted at the tick where it shows
+        std::vector<Request *> finished;
+        for (Request *r : act) {
+            mhd_ctx *c = r->ctx;
+            if (ctx_drain(c) == MHD_OK && !c->host_diag.empty() && c->host_diag.back().nonfinite > 0) r->nsteps = 0;
+            if (c->host_diag.size() > 4) c->host_diag.erase(c->host_diag.begin(), c->host_diag.end() - 4);
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            ticks++;
+            busy_s += tb - ta;
+            cell_substeps += 3.0 * (double)k * cells;
+            const double per = (tb - ta) * 1e3 / (double)k;
+            for (Request *r : act) {
+                r->steps_done += k;
+                for (int64_t q = 0; q < k; q++) step_lat_ms.push_back(per);
+                if (r->steps_done >= r->nsteps) finished.push_back(r);
+            }
+        }
+        for (Request *r : finished) {
+            mhd_ctx *c = r->ctx;
+            // last diagnostics (also flags a run that went non-finite)
+            (void)ctx_drain(c);
+            bool bad = r->steps_done < r->nsteps || r->nsteps == 0;
+            if (!c->host_diag.empty()) {
+                r->em = c->host_diag.back().em;
+                r->brms = c->host_diag.back().brms;
+                for (const auto &d : c->host_diag) bad = bad || d.nonfinite > 0;
+            }
+            if (r->retain) {
+                r->kept.resize(NF);
+                for (int f = 0; f < NF; f++) {
+                    r->kept[f].resize(c->ncell * c->p.precision);
+                    (void)hipMemcpy(r->kept[f].data(), c->bufs[c->parity][f], r->kept[f].size(), hipMemcpyDeviceToHost);
+                }
+            }
+            ctx_release(c);
+            delete c;
+            std::lock_guard<std::mutex> lk(mu);
+            r->ctx = nullptr;
+            r->state = bad ? MHD_RUN_FAILED : MHD_RUN_DONE;
+            r->t_done = now();
+            last_done = r->t_done;
+            e2e_s.push_back(r->t_done - r->t_submit);
+            in_use -= r->footprint;
+            if (bad) n_fail++; else n_done++;
+            active.erase(std::find(active.begin(), active.end(), r->id));
+            set_changed = true;
+        }
+        if (!finished.empty()) cv.notify_all();
+    }
+    running.store(false);
+    cv.notify_all();
+}
+
+extern "C" {
+
+// ---------------------------------------------------------------- batch
+
+mhd_status mhd_batch_create(const mhd_params *runs, int32_t n, void *hip_stream, mhd_batch **out)
+{
+    if (!runs || n <= 0 || !out) return fail(MHD_E_INVALID, "batch: need n > 0 runs and an out pointer");
+    *out = nullptr;
+    for (int32_t i = 0; i < n; i++) {
+        mhd_status st = check_params(&runs[i]);
+        if (st != MHD_OK) return fail(st, "run " + std::to_string(i) + ": " + g_err);
+    }
+    mhd_batch *b = new (std::nothrow) mhd_batch();
+    if (!b) return fail(MHD_E_OOM, "host allocation failed");
+    mhd_status st = b->mr.init_stream(hip_stream);
+    for (int32_t i = 0; i < n && st == MHD_OK; i++) {
+        mhd_ctx *c = new mhd_ctx();
+        st = ctx_init(c, &runs[i], b->mr.stream, nullptr, -1);
+        c->in_batch = true;
+        b->runs.push_back(c);
+    }
+    if (st == MHD_OK) st = b->mr.build(b->runs);
+    if (st != MHD_OK) {
+        const std::string msg = g_err;
+        mhd_batch_destroy(b);
+        return fail(st, msg);
+    }
+    *out = b;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_destroy(mhd_batch *b)
+{
+    if (!b) return MHD_OK;
+    b->mr.clear();
+    for (mhd_ctx *c : b->runs) {
+        ctx_release(c);
+        delete c;
+    }
+    b->mr.destroy_stream();
+    delete b;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_ctx(mhd_batch *b, int32_t i, mhd_ctx **ctx)
+{
+    if (!b || !ctx || i < 0 || i >= (int32_t)b->runs.size()) return fail(MHD_E_INVALID, "batch: run index out of range");
+    *ctx = b->runs[(size_t)i];
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_run(mhd_batch *b, int64_t nsteps, int use_graph)
+{
+    if (!b || nsteps < 0) return fail(MHD_E_INVALID, "batch: bad arguments");
+    return b->mr.run(nsteps, use_graph != 0);
+}
+
+// ---------------------------------------------------------------- server
+
+mhd_status mhd_server_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_tick, void *hip_stream,
+                             mhd_server **out)
+{
+    if (!out || max_slots <= 0 || steps_per_tick <= 0 || hbm_budget == 0)
+        return fail(MHD_E_INVALID, "server: need budget > 0, slots > 0, steps_per_tick > 0");
+    mhd_server *s = new (std::nothrow) mhd_server();
+    if (!s) return fail(MHD_E_OOM, "host allocation failed");
+    s->budget = hbm_budget;
+    s->max_slots = max_slots;
+    s->steps_per_tick = steps_per_tick;
+    mhd_status st = s->mr.init_stream(hip_stream);
+    if (st != MHD_OK) {
+        delete s;
+        return st;
+    }
+    *out = s;
+    return MHD_OK;
+}
+
+mhd_status mhd_server_start(mhd_server *s)
+{
+    if (!s) return fail(MHD_E_INVALID, "server is NULL");
+    if (s->running.load()) return MHD_OK;
+    if (s->worker.joinable()) s->worker.join();
+    s->stop_req.store(false);
+    s->running.store(true);
+    s->worker = std::thread([s]() { s->loop(); });
+    return MHD_OK;
+}
+
+mhd_status mhd_server_submit(mhd_server *s, const mhd_params *p, uint64_t seed, double a_noise, double kf, double f0,
+                             double sigma, int64_t nsteps, int32_t retain, int64_t *id)
+{
+    if (!s || !id) return fail(MHD_E_INVALID, "NULL argument");
+    mhd_status st = check_params(p);
+    if (st != MHD_OK) return st;
+    if (nsteps <= 0) return fail(MHD_E_INVALID, "nsteps must be > 0");
+    if (!(kf >= 1.0) || !std::isfinite(f0) || !std::isfinite(sigma) || !std::isfinite(a_noise))
+        return fail(MHD_E_INVALID, "bad forcing or noise parameters");
+    auto r = std::make_unique<Request>();
+    r->p = *p;
+    r->seed = seed;
+    r->a_noise = a_noise;
+    r->kf = kf;
+    r->f0 = f0;
+    r->sigma = sigma;
+    r->nsteps = nsteps;
+    r->retain = retain != 0;
+    r->footprint = ctx_footprint(*p);
+    if (r->footprint > s->budget) return fail(MHD_E_BUSY, "run footprint exceeds the whole HBM budget");
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->id = s->next_id++;
+    r->t_submit = s->now();
+    if (s->first_submit < 0) s->first_submit = r->t_submit;
+    *id = r->id;
+    s->queue.push_back(r->id);
+    s->reqs[r->id] = std::move(r);
+    s->n_sub++;
+    s->cv.notify_all();
+    return MHD_OK;
+}
+
+mhd_status mhd_server_poll(mhd_server *s, int64_t id, mhd_run_info *info)
+{
+    if (!s || !info) return fail(MHD_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(MHD_E_NOTFOUND, "unknown run id");
+    const Request &r = *it->second;
+    info->state = r.state;
+    info->precision = r.p.precision;
+    info->steps_done = r.steps_done;
+    info->steps_total = r.nsteps;
+    info->t_submit = r.t_submit;
+    info->t_admit = r.t_admit;
+    info->t_done = r.t_done;
+    info->em = r.em;
+    info->brms = r.brms;
+    return MHD_OK;
+}
+
+mhd_status mhd_server_wait(mhd_server *s, int64_t id, double timeout_s)
+{
+    if (!s) return fail(MHD_E_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(MHD_E_NOTFOUND, "unknown run id");
+    Request *r = it->second.get();
+    const auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
+    while (r->state != MHD_RUN_DONE && r->state != MHD_RUN_FAILED) {
+        if (!s->running.load()) {
+            std::string why = s->worker_error.empty() ? "server is not running" : s->worker_error;
+            return fail(MHD_E_DEVICE, "server stopped: " + why);
+        }
+        if (s->cv.wait_until(lk, deadline) == std::cv_status::timeout &&
+            r->state != MHD_RUN_DONE && r->state != MHD_RUN_FAILED)
+            return fail(MHD_E_BUSY, "timed out waiting for the run");
+    }
+    return MHD_OK;
+}
+
+mhd_status mhd_server_get_field(mhd_server *s, int64_t id, int field, void *dst)
+{
+    if (!s || !dst || field < 0 || field >= NF) return fail(MHD_E_INVALID, "bad arguments");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(MHD_E_NOTFOUND, "unknown run id");
+    const Request &r = *it->second;
+    if (r.state != MHD_RUN_DONE && r.state != MHD_RUN_FAILED) return fail(MHD_E_BUSY, "run has not finished");
+    if (r.kept.empty()) return fail(MHD_E_INVALID, "run was not submitted with retain");
+    std::memcpy(dst, r.kept[(size_t)field].data(), r.kept[(size_t)field].size());
+    return MHD_OK;
+}
+
+mhd_status mhd_server_release(mhd_server *s, int64_t id)
+{
+    if (!s) return fail(MHD_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(MHD_E_NOTFOUND, "unknown run id");
+    if (it->second->state != MHD_RUN_DONE && it->second->state != MHD_RUN_FAILED)
+        return fail(MHD_E_BUSY, "run has not finished");
+    s->reqs.erase(it);
+    return MHD_OK;
+}
+
+mhd_status mhd_server_stats_get(mhd_server *s, mhd_server_stats *st)
+{
+    if (!s || !st) return fail(MHD_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(st, 0, sizeof *st);
+    st->submitted = s->n_sub;
+    st->admitted = s->n_adm;
+    st->completed = s->n_done;
+    st->failed = s->n_fail;
+    st->ticks = s->ticks;
+    st->step_samples = (int64_t)s->step_lat_ms.size();
+    st->lat_p50_ms = pct(s->step_lat_ms, 0.50);
+    st->lat_p90_ms = pct(s->step_lat_ms, 0.90);
+    st->lat_p99_ms = pct(s->step_lat_ms, 0.99);
+    st->queue_p50_s = pct(s->queue_s, 0.50);
+    st->queue_p99_s = pct(s->queue_s, 0.99);
+    st->e2e_p50_s = pct(s->e2e_s, 0.50);
+    st->e2e_p99_s = pct(s->e2e_s, 0.99);
+    st->busy_s = s->busy_s;
+    st->wall_s = s->first_submit < 0 ? 0.0 : std::max(0.0, s->last_done - s->first_submit);
+    st->cell_substeps = s->cell_substeps;
+    st->hbm_in_use = s->in_use;
+    st->hbm_peak = s->peak;
+    return MHD_OK;
+}
+
+mhd_status mhd_server_stop(mhd_server *s)
+{
+    if (!s) return fail(MHD_E_INVALID, "server is NULL");
+    s->stop_req.store(true);
+    s->cv.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    s->running.store(false);
+    return MHD_OK;
+}
+
+mhd_status mhd_server_destroy(mhd_server *s)
+{
+    if (!s) return MHD_OK;
+    mhd_server_stop(s);
+    for (auto &kv : s->reqs)
+        if (kv.second->ctx) {
+            ctx_release(kv.second->ctx);
+            delete kv.second->ctx;
+        }
+    s->mr.clear();
+    s->mr.destroy_stream();
+    delete s;
+    return MHD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+"""The C-ABI library loads, exports every symbol the header declares, and its host-only
+logic (argument validation, forcing draws, growth-rate fit, tile shapes) behaves.
+No device work here."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import mhd_inputs as mi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mhd.h")
+
+
+def _mhd():
+    import paper_2012_08758_amd as mhd
+    return mhd
+
+
+def header_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    mhd = _mhd()
+    lib = C.CDLL(mhd.LIB_PATH)
+    syms = header_symbols()
+    assert len(syms) >= 30
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+    # and the binding covers exactly the declared API
+    assert sorted(mhd.EXPORTS) == syms
+
+
+def test_struct_layouts_match_header():
+    mhd = _mhd()
+    assert C.sizeof(mhd.mhd_params) == 4 * 4 + 10 * 8
+    assert C.sizeof(mhd.mhd_forcing) == 4 * 4 + 6 * 8
+    assert C.sizeof(mhd.mhd_diag) == 8 + 11 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=7), dict(ny=4), dict(precision=2), dict(dt=0.0), dict(dt=-1e-3), dict(nu=-1.0),
+    dict(eta=float("nan")), dict(lx=0.0), dict(nx=70000), dict(bext=(0.0, float("inf"), 0.0)),
+])
+def test_invalid_parameters_are_rejected_before_device_work(bad):
+    mhd = _mhd()
+    kw = dict(nu=1e-3, eta=1e-3)
+    n = dict(nx=16, ny=16, nz=16)
+    for k in ("nx", "ny", "nz"):
+        if k in bad:
+            n[k] = bad.pop(k)
+    p = mhd.make_params(n["nx"], n["ny"], n["nz"], **kw)
+    for k, v in bad.items():
+        if k == "bext":
+            for a in range(3):
+                p.bext[a] = v[a]
+        else:
+            setattr(p, k, v)
+    with pytest.raises(mhd.MhdError) as ei:
+        mhd.mhd_create(p)
+    assert ei.value.status == mhd.MHD_E_INVALID
+    assert mhd.lib.mhd_last_error().decode()
+
+
+def test_forcing_draws_match_the_input_generator_bit_for_bit():
+    mhd = _mhd()
+    for kf in (3.0, 5.0):
+        ref = mi.forcing_draws(11, 300, kf)
+        for n in range(300):
+            f = mhd.mhd_forcing_draw(kf, 0.02, 1.0, 11, n)
+            assert tuple(f.k) == ref[n].k
+            assert tuple(f.e) == ref[n].e
+            assert f.phi == ref[n].phi
+            assert f.sigma == 1.0 and f.f0 == 0.02
+
+
+def test_growth_rate_fit_host_side():
+    mhd = _mhd()
+    t = np.arange(50) * 1e-3
+    recs = [dict(t=float(x), brms=float(2e-5 * math.exp(0.031 * x))) for x in t]
+    assert abs(mhd.mhd_growth_rate(recs) - 0.031) < 1e-10
+    assert abs(mhd.mhd_growth_rate(recs, 10, 40) - 0.031) < 1e-10
+    with pytest.raises(mhd.MhdError):
+        mhd.mhd_growth_rate(recs, 5, 6)
+
+
+def test_tile_shapes_and_pinning():
+    mhd = _mhd()
+    n = mhd.mhd_num_tile_shapes()
+    names = [mhd.mhd_tile_shape_name(i) for i in range(n)]
+    assert len(set(names)) == n and all(re.fullmatch(r"\d+x\d+x\d+/\d", s) for s in names)
+    p = mhd.make_params(96, 80, 72, nu=1e-3, eta=1e-3)
+    default = mhd.mhd_tile_config(p)
+    mhd.mhd_set_tile_shape(p, n - 1)
+    assert mhd.mhd_tile_config(p) == names[n - 1]
+    mhd.mhd_set_tile_shape(p, -1)
+    assert mhd.mhd_tile_config(p) == default
+    with pytest.raises(mhd.MhdError):
+        mhd.mhd_set_tile_shape(p, n)
+
+
+def test_binding_refuses_to_run_without_the_library(tmp_path, monkeypatch):
+    """The product path has no fallback: a missing library is an ImportError."""
+    import importlib.util
+    src = os.path.join(ROOT, "paper_2012_08758_amd", "__init__.py")
+    fake = tmp_path / "pkg"
+    fake.mkdir()
+    (fake / "__init__.py").write_text(open(src).read())
+    spec = importlib.util.spec_from_file_location("mhd_nolib", str(fake / "__init__.py"))
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError):
+        spec.loader.exec_module(mod)

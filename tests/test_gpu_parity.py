@@ -1,0 +1,369 @@
+"""HIP path vs the FP64 oracle, through the C ABI, on seeded inputs.
+
+Bars (per field f, per step, from the same input state and forcing records):
+    e_f = ||gpu - oracle||_inf / max(||oracle||_inf, dt * T_f)  <= 1e-12 (FP64), 1e-5 (FP32)
+with T_f the sum over the field's right-hand-side terms of max|term| (the scale that
+roundoff of one step is relative to).  FP32 runs start from FP32 values, which the
+oracle reads promoted exactly to FP64.  Diagnostics (FP64 sums at both precisions)
+must agree to 1e-12 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import mhd_inputs as mi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {8: 1e-12, 4: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def mhd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_08758_amd as m
+    return m
+
+
+def _dtype(prec):
+    return np.float64 if prec == 8 else np.float32
+
+
+def gpu_run(mhd, rp, state, recs, per_step=False, shape=None):
+    """Run len(recs) steps on the GPU.  Returns the list of states after each step
+    (per_step) or the final state, plus the diagnostic records."""
+    p = mhd.params_from(rp)
+    if shape is not None:
+        mhd.mhd_set_tile_shape(p, shape)
+    try:
+        with mhd.Run(p) as run:
+            run.set_state(state.astype(_dtype(rp.precision)))
+            run.set_forcing(recs)
+            outs = []
+            if per_step:
+                for _ in recs:
+                    run.step(1)
+                    outs.append(run.get_state())
+            else:
+                run.step(len(recs))
+                outs.append(run.get_state())
+            mhd.mhd_reduce(run.h)
+            diag = run.diag()
+    finally:
+        if shape is not None:
+            mhd.mhd_set_tile_shape(p, -1)
+    return outs, diag
+
+
+def check_step(got, want, tscale, rp, label):
+    e, plain = oracle.tolerance_error(got, want, tscale, rp.dt)
+    print(f"{label}: e_f = " + " ".join(f"{n}:{x:.2e}" for n, x in zip(mi.FIELD_NAMES, e)), flush=True)
+    assert np.all(e <= TOL[rp.precision]), (label, e, plain)
+    return e
+
+
+def oracle_per_step(st, rp, recs):
+    outs, scales = [], []
+    cur = st.astype(np.float64)
+    for r in recs:
+        cur, ts = oracle.step(cur, rp, [r])
+        outs.append(cur)
+        scales.append(ts[0])
+    return outs, scales
+
+
+# ------------------------------------------------------------------ small grids, every step
+
+@pytest.mark.parametrize("prec", [8, 4])
+def test_config1_32cubed_every_step(mhd, prec):
+    """32^3, nu = eta = 5e-3, non-helical forcing kf = 3, f0 = 0.02, A noise 1e-5, 20 steps."""
+    rp = mi.RunParams(32, 32, 32, nu=5e-3, eta=5e-3, dt=1e-3, precision=prec)
+    st = mi.ic_seed_noise(rp, 0, 1e-5, dtype=_dtype(prec))
+    recs = mi.forcing_schedule(0, 20, 3.0, 0.02, 0.0)
+    got, diag = gpu_run(mhd, rp, st, recs, per_step=True)
+    want, scales = oracle_per_step(st, rp, recs)
+    for n in range(20):
+        check_step(got[n], want[n], scales[n], rp, f"cfg1 fp{8 * prec} step {n + 1}")
+    # diagnostics of the input state of every step, and of the final state
+    assert len(diag) == 21
+    states = [st.astype(np.float64)] + want
+    for n, rec in enumerate(diag):
+        ref = oracle.diag(states[n] if prec == 8 else
+                          (states[n] if n == 0 else got[n - 1].astype(np.float64)), rp)
+        assert rec["step"] == n and abs(rec["t"] - n * rp.dt) < 1e-15
+        for k in ("em", "ek", "urms", "brms", "umax"):
+            assert abs(rec[k] - ref[k]) <= 1e-12 * abs(ref[k]) + 1e-300, (n, k, rec[k], ref[k])
+
+
+@pytest.mark.parametrize("shape", range(6))
+def test_every_tile_shape_ragged_grid_fp64(mhd, shape):
+    rp = mi.RunParams(20, 18, 13, nu=4e-3, eta=6e-3, dt=1e-3, precision=8, bext=(0.01, 0.0, -0.02))
+    st = mi.noise_state(rp, 5 + shape, 0.2, 0.2, 0.2)
+    recs = mi.forcing_schedule(3, 2, 3.0, 0.05, 1.0)
+    got, _ = gpu_run(mhd, rp, st, recs, per_step=True, shape=shape)
+    want, scales = oracle_per_step(st, rp, recs)
+    for n in range(2):
+        check_step(got[n], want[n], scales[n], rp, f"shape {shape} step {n + 1}")
+
+
+@pytest.mark.parametrize("shape", [0, 3, 5])
+def test_tile_shapes_fp32(mhd, shape):
+    rp = mi.RunParams(24, 20, 17, nu=4e-3, eta=6e-3, dt=1e-3, precision=4)
+    st = mi.noise_state(rp, 7, 0.2, 0.2, 0.2, dtype=np.float32)
+    recs = mi.forcing_schedule(4, 2, 3.0, 0.05, 0.5)
+    got, _ = gpu_run(mhd, rp, st, recs, per_step=True, shape=shape)
+    want, scales = oracle_per_step(st, rp, recs)
+    for n in range(2):
+        check_step(got[n], want[n], scales[n], rp, f"fp32 shape {shape} step {n + 1}")
+
+
+@pytest.mark.parametrize("n", [8, 9, 33])
+def test_small_and_odd_grids(mhd, n):
+    """Grids smaller than a tile (the halo wraps more than once) and odd sizes."""
+    rp = mi.RunParams(n, n, n, nu=1e-2, eta=1e-2, dt=1e-3, precision=8)
+    st = mi.smooth_state(rp, 2, kmax=2)
+    recs = mi.forcing_schedule(9, 3, 3.0, 0.02, 1.0)
+    got, _ = gpu_run(mhd, rp, st, recs, per_step=True)
+    want, scales = oracle_per_step(st, rp, recs)
+    for k in range(3):
+        check_step(got[k], want[k], scales[k], rp, f"{n}^3 step {k + 1}")
+
+
+def test_forcing_off_and_bext_alfven_state(mhd):
+    """No forcing records (f0 = 0) and an imposed field: exercises the Lorentz/induction pair."""
+    rp = mi.RunParams(16, 16, 32, nu=1e-2, eta=1e-2, dt=1e-2, precision=8, bext=(0.0, 0.0, 1.0))
+    st = mi.smooth_state(rp, 12, kmax=3, amp_lnrho=0.05, amp_u=0.1, amp_a=0.1)
+    recs = mi.no_forcing(4)
+    got, _ = gpu_run(mhd, rp, st, recs, per_step=True)
+    want, scales = oracle_per_step(st, rp, recs)
+    for k in range(4):
+        check_step(got[k], want[k], scales[k], rp, f"bext step {k + 1}")
+
+
+# ------------------------------------------------------------------ full sizes, sampled
+
+def _sample_cells(rp, n, seed):
+    rng = np.random.default_rng(seed)
+    cells = rng.integers(0, rp.ncell, size=n)
+    # faces, edges and corners of the periodic box
+    corners = []
+    for x in (0, rp.nx - 1):
+        for y in (0, rp.ny - 1):
+            for z in (0, rp.nz - 1):
+                corners.append(x + rp.nx * (y + rp.ny * z))
+    return np.unique(np.concatenate([cells, corners]))
+
+
+@pytest.mark.parametrize("n,prec,sigma,nu", [(256, 8, 1.0, 1e-3), (512, 8, 0.0, 4e-4), (512, 4, 0.0, 4e-4)])
+def test_full_size_sampled_one_step(mhd, n, prec, sigma, nu):
+    """256^3 (helical, nu = eta = 1e-3) and 512^3 (non-helical, 4e-4) in FP64 and FP32, in
+    the launch configuration the benchmark uses: one step from a seeded state, compared
+    with the oracle's step at sampled cells (its dependency cone, evaluated cell by cell)."""
+    rp = mi.RunParams(n, n, n, nu=nu, eta=nu, dt=1e-3, precision=prec)
+    print(f"generating {n}^3 state", flush=True)
+    st = mi.noise_state(rp, 21, 0.05, 0.05, 0.05, dtype=_dtype(prec))
+    rec = mi.forcing_schedule(0, 1, 3.0, 0.02, sigma)[0]
+    got, _ = gpu_run(mhd, rp, st, [rec])
+    got = got[0].reshape(7, -1)
+    cells = _sample_cells(rp, 400, n)
+    st64 = st.astype(np.float64) if prec == 4 else st
+    want = oracle.step_cells(st64, rp, rec, cells)
+    terms = oracle.terms_cells(st64, rp, rec, cells).max(axis=0).sum(axis=1)
+    g = got[:, cells].T.astype(np.float64)
+    d = np.abs(g - want).max(axis=0)
+    den = np.maximum(np.abs(want).max(axis=0), rp.dt * terms)
+    e = d / den
+    print(f"{n}^3 fp{8 * prec} sampled e_f: " + " ".join(f"{x:.2e}" for x in e), flush=True)
+    assert np.all(e <= TOL[prec]), e
+
+
+# ------------------------------------------------------------------ diagnostics
+
+@pytest.mark.parametrize("prec", [8, 4])
+def test_diagnostics_match_oracle(mhd, prec):
+    rp = mi.RunParams(24, 20, 16, nu=1e-3, eta=1e-3, dt=1e-3, precision=prec, bext=(0.1, 0.0, 0.0))
+    st = mi.noise_state(rp, 31, 0.3, 0.3, 0.3, dtype=_dtype(prec))
+    with mhd.Run(mhd.params_from(rp)) as run:
+        run.set_state(st)
+        mhd.mhd_reduce(run.h)
+        rec = run.diag()[-1]
+    ref = oracle.diag(st.astype(np.float64), rp)
+    for k in ("em", "ek", "urms", "brms", "umax", "lnrho_mean", "bx_mean", "by_mean", "bz_mean"):
+        scale = max(abs(ref[k]), 1e-3 * ref["brms"] if k.startswith("b") else abs(ref[k]))
+        assert abs(rec[k] - ref[k]) <= 1e-12 * max(scale, 1e-300), (k, rec[k], ref[k])
+    assert rec["nonfinite"] == 0
+
+
+def test_nonfinite_cells_are_counted(mhd):
+    rp = mi.RunParams(16, 16, 16, nu=1e-3, eta=1e-3, precision=8)
+    st = mi.noise_state(rp, 1)
+    st[2, 3, 4, 5] = np.nan
+    st[6, 0, 0, 0] = np.inf
+    st[6, 1, 0, 0] = -np.inf
+    with mhd.Run(mhd.params_from(rp)) as run:
+        run.set_state(st)
+        mhd.mhd_reduce(run.h)
+        assert run.diag()[-1]["nonfinite"] == 3
+
+
+def test_beltrami_growth_rate_on_gpu(mhd):
+    """Decaying Beltrami field: B_rms falls by |G(-eta k2^2 dt)| per step exactly; the GPU's
+    FP64 series and host fit give lambda = ln|G| / dt."""
+    rp = mi.RunParams(8, 8, 32, nu=0.1, eta=0.1, dt=0.02, precision=8)
+    z = np.arange(32) * (2 * math.pi / 32)
+    k = 2
+    st = np.zeros((7, 32, 8, 8))
+    st[4] = (np.sin(k * z) / k)[:, None, None]
+    st[5] = (np.cos(k * z) / k)[:, None, None]
+    w = k * 2 * math.pi / 32
+    k2 = (3 * (1 - math.cos(w)) - 0.3 * (1 - math.cos(2 * w)) + (1 - math.cos(3 * w)) / 45) / (2 * math.pi / 32) ** 2
+    zz = -rp.eta * k2 * rp.dt
+    G = 1 + zz + zz * zz / 2 + zz ** 3 / 6
+    _, diag = gpu_run(mhd, rp, st, mi.no_forcing(10))
+    lam = mhd.mhd_growth_rate(diag)
+    assert abs(lam - math.log(abs(G)) / rp.dt) < 1e-10
+
+
+# ------------------------------------------------------------------ runtime properties
+
+def test_init_seed_matches_input_generator(mhd):
+    rp = mi.RunParams(20, 16, 12, nu=1e-3, eta=1e-3, precision=8)
+    want = mi.ic_seed_noise(rp, 42, 1e-5)
+    with mhd.Run(mhd.params_from(rp)) as run:
+        mhd.mhd_init_seed(run.h, 42, 1e-5)
+        got = run.get_state()
+    assert np.all(got[:4] == 0)
+    assert np.max(np.abs(got - want)) <= 1e-15 * np.max(np.abs(want))
+
+
+def test_bitwise_deterministic_and_resumable(mhd):
+    rp = mi.RunParams(24, 24, 24, nu=2e-3, eta=2e-3, precision=8)
+    st = mi.noise_state(rp, 3, 0.1, 0.1, 0.1)
+    recs = mi.forcing_schedule(5, 6, 3.0, 0.02, 1.0)
+    a, _ = gpu_run(mhd, rp, st, recs)
+    b, _ = gpu_run(mhd, rp, st, recs)
+    assert np.array_equal(a[0], b[0])
+    # checkpoint / resume: 3 steps, copy the state out, new context, 3 more steps
+    h1, _ = gpu_run(mhd, rp, st, recs[:3])
+    h2, _ = gpu_run(mhd, rp, h1[0], recs[3:])
+    assert np.array_equal(h2[0], a[0])
+
+
+def test_borrowed_torch_buffers(mhd):
+    import torch
+    rp = mi.RunParams(16, 12, 20, nu=2e-3, eta=2e-3, precision=4)
+    st = mi.noise_state(rp, 8, 0.1, 0.1, 0.1, dtype=np.float32)
+    recs = mi.forcing_schedule(6, 3, 3.0, 0.02, 0.0)
+    ref, _ = gpu_run(mhd, rp, st, recs)
+    bufs = torch.zeros((14, rp.ncell), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    h = mhd.mhd_create_borrowed(mhd.params_from(rp), [bufs[i] for i in range(14)], stream)
+    try:
+        bufs[:7].copy_(torch.from_numpy(st.reshape(7, -1)))
+        torch.cuda.synchronize()
+        mhd.mhd_set_forcing(h, recs)
+        mhd.mhd_step(h, 3)
+        mhd.mhd_sync(h)
+        par = 1 if mhd.mhd_field_ptr(h, 0) == bufs[7].data_ptr() else 0
+        got = bufs[7 * par:7 * par + 7].cpu().numpy().reshape(ref[0].shape)
+    finally:
+        mhd.mhd_destroy(h)
+    assert np.array_equal(got, ref[0])
+
+
+def _batch_specs():
+    return [mi.RunParams(16, 16, 16, nu=5e-3, eta=5e-3, precision=8),
+            mi.RunParams(24, 20, 16, nu=2e-3, eta=2e-3, precision=8),
+            mi.RunParams(32, 32, 32, nu=1e-3, eta=1e-3, precision=4),
+            mi.RunParams(20, 20, 24, nu=4e-4, eta=4e-4, precision=4)]
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batched_ensemble_equals_runs_alone(mhd, use_graph):
+    specs = _batch_specs()
+    states = [mi.noise_state(rp, 40 + i, 0.1, 0.1, 0.1, dtype=_dtype(rp.precision)) for i, rp in enumerate(specs)]
+    scheds = [mi.forcing_schedule(50 + i, 7, 3.0, 0.02, float(i % 2)) for i in range(len(specs))]
+    alone = [gpu_run(mhd, rp, s, r)[0][0] for rp, s, r in zip(specs, states, scheds)]
+    b = mhd.mhd_batch_create([mhd.params_from(rp) for rp in specs])
+    try:
+        ctxs = [mhd.mhd_batch_ctx(b, i) for i in range(len(specs))]
+        for c, s, r in zip(ctxs, states, scheds):
+            for f in range(7):
+                mhd.mhd_set_field(c, f, np.ascontiguousarray(s[f]))
+            mhd.mhd_set_forcing(c, r)
+        mhd.mhd_batch_run(b, 4, use_graph)
+        mhd.mhd_batch_run(b, 3, use_graph)
+        for i, (c, rp) in enumerate(zip(ctxs, specs)):
+            got = np.empty_like(alone[i])
+            for f in range(7):
+                mhd.mhd_get_field(c, f, got[f])
+            assert np.array_equal(got, alone[i]), f"run {i} differs in the batch"
+            assert len(mhd.mhd_get_diag(c)) == 7
+    finally:
+        mhd.mhd_batch_destroy(b)
+
+
+def test_server_continuous_batching_equals_alone(mhd):
+    """Runs that arrive while others are in flight are admitted by footprint, advance
+    together, and finish with exactly the state they reach alone."""
+    specs = [(16, 8, 30), (24, 4, 45), (32, 4, 20), (16, 4, 60), (20, 8, 25), (28, 8, 40)]
+    params = [mi.RunParams(n, n, n, nu=3e-3, eta=3e-3, precision=prec) for n, prec, _ in specs]
+    budget = 3 * 14 * 8 * 28 ** 3 + (1 << 22)
+    srv = mhd.mhd_server_create(budget, 4, 5)
+    ids = []
+    try:
+        mhd.mhd_server_start(srv)
+        for j, (rp, (_, _, steps)) in enumerate(zip(params, specs)):
+            ids.append(mhd.mhd_server_submit(srv, mhd.params_from(rp), 100 + j, 1e-3, 3.0, 0.02,
+                                             float(j % 2), steps, retain=True))
+        for rid in ids:
+            mhd.mhd_server_wait(srv, rid, 120.0)
+        st = mhd.mhd_server_stats_get(srv)
+        assert st.completed == len(specs) and st.failed == 0
+        assert st.hbm_peak <= budget and st.lat_p99_ms > 0
+        assert st.step_samples == sum(s for _, _, s in specs)
+        for j, (rid, rp, (_, _, steps)) in enumerate(zip(ids, params, specs)):
+            info = mhd.mhd_server_poll(srv, rid)
+            assert info.state == mhd.MHD_RUN_DONE and info.steps_done == steps
+            with mhd.Run(mhd.params_from(rp)) as run:
+                mhd.mhd_init_seed(run.h, 100 + j, 1e-3)
+                mhd.mhd_set_forcing_random(run.h, 3.0, 0.02, float(j % 2), 100 + j)
+                run.step(steps)
+                want = run.get_state()
+            got = np.empty_like(want)
+            for f in range(7):
+                mhd.mhd_server_get_field(srv, rid, f, got[f])
+            assert np.array_equal(got, want), f"served run {j} differs from the run alone"
+    finally:
+        mhd.mhd_server_destroy(srv)
+
+
+def test_server_evicts_a_run_that_goes_nonfinite(mhd):
+    """A run with an unstable time step is flagged and evicted; a co-resident run is unaffected."""
+    good = mi.RunParams(16, 16, 16, nu=3e-3, eta=3e-3, precision=8)
+    bad = mi.RunParams(16, 16, 16, nu=3e-3, eta=3e-3, dt=5.0, precision=8)
+    srv = mhd.mhd_server_create(1 << 30, 4, 2)
+    try:
+        mhd.mhd_server_start(srv)
+        ig = mhd.mhd_server_submit(srv, mhd.params_from(good), 1, 1e-3, 3.0, 0.02, 1.0, 40, retain=True)
+        ib = mhd.mhd_server_submit(srv, mhd.params_from(bad), 2, 1.0, 3.0, 5.0, 1.0, 4000, retain=False)
+        mhd.mhd_server_wait(srv, ig, 60.0)
+        mhd.mhd_server_wait(srv, ib, 60.0)
+        assert mhd.mhd_server_poll(srv, ib).state == mhd.MHD_RUN_FAILED
+        assert mhd.mhd_server_poll(srv, ib).steps_done < 4000
+        assert mhd.mhd_server_poll(srv, ig).state == mhd.MHD_RUN_DONE
+        with mhd.Run(mhd.params_from(good)) as run:
+            mhd.mhd_init_seed(run.h, 1, 1e-3)
+            mhd.mhd_set_forcing_random(run.h, 3.0, 0.02, 1.0, 1)
+            run.step(40)
+            want = run.get_state()
+        got = np.empty_like(want)
+        for f in range(7):
+            mhd.mhd_server_get_field(srv, ig, f, got[f])
+        assert np.array_equal(got, want)
+    finally:
+        mhd.mhd_server_destroy(srv)
