@@ -67,6 +67,22 @@ def single_run(mhd, n, prec, warmup, steps, nu=4e-4):
         ns_per_point_step=ms * 1e6 / cells)
 
 
+def shape_sweep(mhd, n, steps=3):
+    out = {}
+    for prec in (mhd.MHD_FP64, mhd.MHD_FP32):
+        p = mhd.make_params(n, nu=4e-4, eta=4e-4, dt=1e-3, precision=prec)
+        for i in range(mhd.mhd_num_tile_shapes()):
+            mhd.mhd_set_tile_shape(p, i)
+            try:
+                r = single_run(mhd, n, prec, 1, steps)
+            finally:
+                mhd.mhd_set_tile_shape(p, -1)
+            key = f"fp{8 * prec}:{mhd.mhd_tile_shape_name(i)}"
+            out[key] = dict(ms_per_step=r["ms_per_step"], substep_kernel_gbs=r["substep_kernel_gbs"])
+            log(f"[bench] shape {key}: {r['ms_per_step']:.2f} ms/step, {r['substep_kernel_gbs']:.0f} GB/s")
+    return out
+
+
 def cpu_baseline(n=512, nz=64, seed=0):
     """The oracle, as it stands, on a bounded sample of the 512^3 workload: one full RK3
     step of an n x n x nz periodic box (same per-cell work), all host cores."""
@@ -228,6 +244,10 @@ def main():
     ap.add_argument("--serve-runs", type=int, default=40)
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--cpu-nz", type=int, default=64)
+    ap.add_argument("--copy-probe-gb", type=float, default=0.0,
+                    help="first run a plain device copy of this many GiB (reference for HBM counters)")
+    ap.add_argument("--sweep-shapes", action="store_true",
+                    help="time every compiled tile shape at the benchmark size (both precisions)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -239,6 +259,19 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     import paper_2012_08758_amd as mhd
+
+    if args.copy_probe_gb > 0:
+        nel = int(args.copy_probe_gb * 2 ** 30) // 4
+        a = torch.ones(nel, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_gb} GiB read + written")
+        del a, b
+    sweep = None
+    if args.sweep_shapes:
+        sweep = shape_sweep(mhd, args.n)
 
     log(f"[bench] {args.n}^3 FP64: {args.warmup} warm-up + {args.steps} timed steps")
     r64 = single_run(mhd, args.n, mhd.MHD_FP64, args.warmup, args.steps)
@@ -303,6 +336,8 @@ def main():
         "ensemble": ens,
         "serving": srv,
     }
+    if sweep is not None:
+        out["shape_sweep"] = sweep
     print(json.dumps(out), flush=True)
 
 
