@@ -45,27 +45,53 @@ static inline double sm_unif(uint64_t key, uint64_t ctr)
 // ------------------------------------------------------------------ tile shapes
 
 const Shape SHAPES[NSHAPES] = {
-    {16, 8, 4, 1},   // 0: 512 threads, halo box / cells = 6.0
-    {32, 8, 4, 1},   // 1: 1024 threads, 5.2
-    {8, 8, 4, 1},    // 2: 256 threads, small grids
-    {16, 8, 8, 2},   // 3: 512 threads, 1024 cells, 4.2
-    {32, 4, 4, 1},   // 4: 512 threads, 7.4
-    {16, 16, 4, 2},  // 5: 512 threads, 1024 cells, 4.7
+    // register-staged kernel: any grid
+    {16, 8, 4, 1, false},   // 0: 512 threads, halo box / cells = 6.0
+    {32, 8, 4, 1, false},   // 1: 1024 threads, 5.2
+    {8, 8, 4, 1, false},    // 2: 256 threads, small grids
+    {16, 8, 8, 2, false},   // 3: 512 threads, 1024 cells, 4.2
+    {32, 4, 4, 1, false},   // 4: 512 threads, 7.4
+    {16, 16, 4, 2, false},  // 5: 512 threads, 1024 cells, 4.7
+    // direct-to-LDS ring kernel: nx a multiple of 16 / sizeof(value), 16-byte aligned fields
+    {16, 8, 4, 1, true},    // 6
+    {32, 8, 4, 1, true},    // 7
+    {8, 8, 4, 1, true},     // 8
+    {16, 8, 8, 2, true},    // 9
+    {32, 4, 4, 1, true},    // 10
+    {16, 16, 4, 2, true},   // 11
 };
 
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int>, int> g_tuned;  // (nx, ny, nz, prec) -> shape
 
-int default_shape(const mhd_params &p)
+bool shape_eligible(const mhd_params &p, int shape, bool aligned)
 {
+    if (shape < 0 || shape >= NSHAPES) return false;
+    if (!SHAPES[shape].pipe) return true;
+    const int epl = 16 / p.precision;
+    return aligned && p.nx % epl == 0;
+}
+
+bool shape_fits(const mhd_params &p, int shape)
+{
+    const Shape &s = SHAPES[shape];
+    return p.nx >= s.tx + 8 && p.ny >= s.ty + 6 && p.nz >= s.tz + 6;
+}
+
+int default_shape(const mhd_params &p, bool aligned)
+{
+    int want = -1;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(std::make_tuple(p.nx, p.ny, p.nz, p.precision));
-        if (it != g_tuned.end()) return it->second;
+        if (it != g_tuned.end()) want = it->second;
     }
-    const double n = (double)p.nx * p.ny * p.nz;
-    if (n <= 64.0 * 64 * 64) return 2;
-    return 0;
+    if (want < 0) {
+        const double n = (double)p.nx * p.ny * p.nz;
+        want = n <= 64.0 * 64 * 64 ? 8 : 6;
+    }
+    if (!shape_eligible(p, want, aligned)) want = SHAPES[want].pipe ? want - 6 : want;
+    return want;
 }
 
 // ------------------------------------------------------------------ coefficients
@@ -319,9 +345,32 @@ static hipError_t launch_shape(int kind, const RunDesc<T> *runs, const TileEnt *
     return hipGetLastError();
 }
 
+template <typename T, int TX, int TY, int TZ, int CZ, bool FIT>
+static hipError_t launch_pipe(int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles, int step,
+                              hipStream_t st)
+{
+    constexpr int W = 2;
+    const dim3 grid(ntiles), block(TX * TY * (TZ / CZ));
+    switch (kind) {
+    case 0: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 0, true, true, W, FIT>), grid, block, 0, st, runs, tiles, step); break;
+    case 1: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 1, false, true, W, FIT>), grid, block, 0, st, runs, tiles, step); break;
+    case 2: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 2, false, true, W, FIT>), grid, block, 0, st, runs, tiles, step); break;
+    default: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 0, true, false, W, FIT>), grid, block, 0, st, runs, tiles, step); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int TX, int TY, int TZ, int CZ>
+static hipError_t launch_pipe_fit(bool fit, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles,
+                                  int step, hipStream_t st)
+{
+    return fit ? launch_pipe<T, TX, TY, TZ, CZ, true>(kind, runs, tiles, ntiles, step, st)
+               : launch_pipe<T, TX, TY, TZ, CZ, false>(kind, runs, tiles, ntiles, step, st);
+}
+
 template <typename T>
-hipError_t launch_substep(int shape, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles, int step,
-                          hipStream_t st)
+hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles,
+                          int step, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
     switch (shape) {
@@ -330,7 +379,13 @@ hipError_t launch_substep(int shape, int kind, const RunDesc<T> *runs, const Til
     case 2: return launch_shape<T, 8, 8, 4, 1>(kind, runs, tiles, ntiles, step, st);
     case 3: return launch_shape<T, 16, 8, 8, 2>(kind, runs, tiles, ntiles, step, st);
     case 4: return launch_shape<T, 32, 4, 4, 1>(kind, runs, tiles, ntiles, step, st);
-    default: return launch_shape<T, 16, 16, 4, 2>(kind, runs, tiles, ntiles, step, st);
+    case 5: return launch_shape<T, 16, 16, 4, 2>(kind, runs, tiles, ntiles, step, st);
+    case 6: return launch_pipe_fit<T, 16, 8, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
+    case 7: return launch_pipe_fit<T, 32, 8, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
+    case 8: return launch_pipe_fit<T, 8, 8, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
+    case 9: return launch_pipe_fit<T, 16, 8, 8, 2>(fit, kind, runs, tiles, ntiles, step, st);
+    case 10: return launch_pipe_fit<T, 32, 4, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
+    default: return launch_pipe_fit<T, 16, 16, 4, 2>(fit, kind, runs, tiles, ntiles, step, st);
     }
 }
 
@@ -342,8 +397,8 @@ hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int step, hipStrea
     return hipGetLastError();
 }
 
-template hipError_t launch_substep<float>(int, int, const RunDesc<float> *, const TileEnt *, int, int, hipStream_t);
-template hipError_t launch_substep<double>(int, int, const RunDesc<double> *, const TileEnt *, int, int, hipStream_t);
+template hipError_t launch_substep<float>(int, bool, int, const RunDesc<float> *, const TileEnt *, int, int, hipStream_t);
+template hipError_t launch_substep<double>(int, bool, int, const RunDesc<double> *, const TileEnt *, int, int, hipStream_t);
 template hipError_t launch_finalize<float>(const RunDesc<float> *, int, int, hipStream_t);
 template hipError_t launch_finalize<double>(const RunDesc<double> *, int, int, hipStream_t);
 
@@ -395,15 +450,17 @@ mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *
     c->p = *p;
     c->ncell = (size_t)p->nx * p->ny * p->nz;
     c->stream = (hipStream_t)stream;
-    c->shape = shape >= 0 ? shape : default_shape(*p);
-    c->ntiles = run_ntiles(*p, c->shape);
     c->fstride = forcing_stride(*p);
     const size_t fb = align_up(c->ncell * (size_t)p->precision, 256);
+    bool aligned = true;
     if (bufs) {
         for (int s = 0; s < 2; s++)
             for (int f = 0; f < NF; f++) {
                 c->bufs[s][f] = bufs[s * NF + f];
                 if (!c->bufs[s][f]) return fail(MHD_E_INVALID, "borrowed buffer is NULL");
+                if ((uintptr_t)c->bufs[s][f] % (uintptr_t)p->precision != 0)
+                    return fail(MHD_E_INVALID, "borrowed buffer is not aligned to its value size");
+                aligned = aligned && ((uintptr_t)c->bufs[s][f] % 16 == 0);
             }
     } else {
         if (hipMalloc(&c->mem, 14 * fb) != hipSuccess) return fail(MHD_E_OOM, "device allocation of the state failed");
@@ -413,6 +470,12 @@ mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *
         if (hipMemsetAsync(c->mem, 0, 14 * fb, c->stream) != hipSuccess)
             return fail(MHD_E_DEVICE, "clearing the state failed");
     }
+    // tile shape: the requested one if this grid and these buffers can use it, else the
+    // (tuned or default) choice; ring shapes fall back to the staged kernel of the same box
+    if (shape >= 0 && !shape_eligible(*p, shape, aligned)) shape = SHAPES[shape].pipe ? shape - 6 : shape;
+    c->shape = shape >= 0 ? shape : default_shape(*p, aligned);
+    c->fit = SHAPES[c->shape].pipe && shape_fits(*p, c->shape);
+    c->ntiles = run_ntiles(*p, c->shape);
     mhd_status st = ctx_alloc_aux(c);
     if (st != MHD_OK) return st;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(MHD_E_DEVICE, "stream sync failed");
@@ -559,10 +622,10 @@ static mhd_status ctx_step_t(mhd_ctx *c, int64_t nsteps)
         if (st != MHD_OK) return st;
         const RunDesc<T> *d = (const RunDesc<T> *)c->d_desc;
         for (int64_t s = 0; s < m; s++) {
-            hipError_t e = launch_substep<T>(c->shape, 0, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            hipError_t e = launch_substep<T>(c->shape, c->fit, 0, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = launch_finalize<T>(d, 1, (int)s, c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, 1, d, c->d_tiles, c->ntiles, (int)s, c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, 2, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
         }
         c->rcount += m;
@@ -600,13 +663,13 @@ static mhd_status ctx_step_timed_t(mhd_ctx *c, int64_t nsteps, double kms[4], do
         for (int64_t s = 0; s < m; s++) {
             hipEvent_t *E = &ev[(size_t)(5 * s)];
             hipError_t e = hipEventRecord(E[0], c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, 0, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 0, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[1], c->stream);
             if (e == hipSuccess) e = launch_finalize<T>(d, 1, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[2], c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, 1, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[3], c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, 2, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[4], c->stream);
             if (e != hipSuccess) return fail_ev(std::string("launch failed: ") + hipGetErrorString(e));
         }
@@ -644,7 +707,7 @@ static mhd_status ctx_reduce_t(mhd_ctx *c)
     mhd_status st = ctx_stage<T>(c, 0, true);
     if (st != MHD_OK) return st;
     const RunDesc<T> *d = (const RunDesc<T> *)c->d_desc;
-    hipError_t e = launch_substep<T>(c->shape, 3, d, c->d_tiles, c->ntiles, 0, c->stream);
+    hipError_t e = launch_substep<T>(c->shape, c->fit, 3, d, c->d_tiles, c->ntiles, 0, c->stream);
     if (e == hipSuccess) e = launch_finalize<T>(d, 1, 0, c->stream);
     if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     c->rcount += 1;
@@ -908,7 +971,7 @@ mhd_status mhd_tile_config(const mhd_params *p, char *buf, size_t len)
     if (st != MHD_OK) return st;
     if (!buf || len == 0) return fail(MHD_E_INVALID, "buffer is NULL");
     const Shape &s = SHAPES[default_shape(*p)];
-    std::snprintf(buf, len, "%dx%dx%d/%d", s.tx, s.ty, s.tz, s.cz);
+    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.pipe ? "+ring" : "");
     return MHD_OK;
 }
 
@@ -926,7 +989,7 @@ mhd_status mhd_tile_shape_name(int32_t i, char *buf, size_t len)
 {
     if (i < 0 || i >= NSHAPES || !buf || len == 0) return fail(MHD_E_INVALID, "bad tile shape index or buffer");
     const Shape &s = SHAPES[i];
-    std::snprintf(buf, len, "%dx%dx%d/%d", s.tx, s.ty, s.tz, s.cz);
+    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.pipe ? "+ring" : "");
     return MHD_OK;
 }
 
@@ -954,6 +1017,7 @@ mhd_status mhd_autotune(const mhd_params *p, int reps, void *hip_stream, double 
     int best = -1;
     double bt = 1e300;
     for (int sh = 0; sh < NSHAPES; sh++) {
+        if (!shape_eligible(*p, sh, true)) continue;
         mhd_ctx *c = new mhd_ctx();
         st = ctx_init(c, p, hip_stream, nullptr, sh);
         if (st == MHD_OK) st = ctx_step(c, 1);  // warm-up

@@ -246,6 +246,101 @@ __device__ __forceinline__ void stage_store(T *dst, const T (&stage)[NL], int ti
     }
 }
 
+// Forcing, RK3 update and diagnostic partials of this thread's cells (shared by
+// both substep kernels).  `red` is LDS scratch of at least 9 doubles per wave,
+// free once every thread has passed the preceding barrier.
+template <typename T, int CZ, int NT, int SUB, bool DIAG, bool STORE>
+__device__ __forceinline__ void finish(Cells<T, CZ> &C, const RunDesc<T> &r, const TileEnt &te, const Coef<T> &K,
+                                       const DCoef &dc, const bool (&inside)[CZ], const uint32_t (&gcell)[CZ],
+                                       const int (&gpos)[CZ][3], G<T> *const (&out)[NF], double *red, int step,
+                                       int tid)
+{
+    if constexpr (STORE) {
+        // forcing (held fixed over the step's substeps)
+        const G<T> *fs = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
+        if (fs[6] != T(0)) {
+            const G<T> *Ex = fs + FHEAD, *Ey = Ex + 2 * r.nx, *Ez = Ey + 2 * r.ny;
+#pragma unroll
+            for (int c = 0; c < CZ; c++) {
+                if (!inside[c]) continue;
+                const int gx = gpos[c][0], gy = gpos[c][1], gz = gpos[c][2];
+                const T xr = Ex[2 * gx], xi = Ex[2 * gx + 1];
+                const T yr = Ey[2 * gy], yi = Ey[2 * gy + 1];
+                const T zr = Ez[2 * gz], zi = Ez[2 * gz + 1];
+                const T pr = xr * yr - xi * yi, pi = xr * yi + xi * yr;
+                const T cr = pr * zr - pi * zi, ci = pr * zi + pi * zr;
+#pragma unroll
+                for (int a = 0; a < 3; a++) C.R[c][1 + a] += fs[a] * cr + fs[3 + a] * ci;
+            }
+        }
+
+        const T bdt = K.bdt[SUB], brho = K.brho[SUB];
+#pragma unroll
+        for (int c = 0; c < CZ; c++) {
+            if (!inside[c]) continue;
+#pragma unroll
+            for (int f = 0; f < NF; f++) {
+                T o;
+                if constexpr (SUB == 0) {
+                    o = C.v[c][f] + bdt * C.R[c][f];
+                } else {
+                    const T old = out[f][gcell[c]];
+                    o = C.v[c][f] + brho * (C.v[c][f] - old) + bdt * C.R[c][f];
+                }
+                out[f][gcell[c]] = o;
+            }
+        }
+    }
+
+    if constexpr (DIAG) {
+        double acc[9];
+#pragma unroll
+        for (int q = 0; q < 9; q++) acc[q] = 0.0;
+#pragma unroll
+        for (int c = 0; c < CZ; c++) {
+            if (!inside[c]) continue;
+            const double bx = C.Bd[c][0] + dc.bext[0], by = C.Bd[c][1] + dc.bext[1], bz = C.Bd[c][2] + dc.bext[2];
+            const double ux = (double)C.v[c][1], uy = (double)C.v[c][2], uz = (double)C.v[c][3];
+            const double u2 = ux * ux + uy * uy + uz * uz;
+            const double b2 = bx * bx + by * by + bz * bz;
+            acc[0] += b2;
+            acc[1] += u2;
+            acc[2] += exp((double)C.v[c][0]) * u2;
+            acc[3] += (double)C.v[c][0];
+            acc[4] += bx;
+            acc[5] += by;
+            acc[6] += bz;
+            acc[7] = fmax(acc[7], u2);
+            bool ok = true;
+#pragma unroll
+            for (int f = 0; f < NF; f++) ok = ok && finite_v(C.v[c][f]);
+            acc[8] += ok ? 0.0 : 1.0;
+        }
+        // wave reduction, then across waves through LDS (fixed order: deterministic)
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double w = __shfl_xor(acc[q], o, 64);
+                acc[q] = (q == 7) ? fmax(acc[q], w) : acc[q] + w;
+            }
+        }
+        constexpr int NW = NT / 64;
+        __syncthreads();
+        const int wave = tid / 64, lane = tid % 64;
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 9; q++) red[wave * 9 + q] = acc[q];
+        }
+        __syncthreads();
+        if (tid < 9) {
+            double sum = red[tid];
+            for (int w = 1; w < NW; w++) sum = (tid == 7) ? fmax(sum, red[w * 9 + tid]) : sum + red[w * 9 + tid];
+            ((G<double> *)r.partials)[(size_t)te.tir * DIAGW + tid] = sum;
+        }
+    }
+}
+
 template <typename T, int TX, int TY, int TZ, int CZ, int SUB, bool DIAG, bool STORE, int WPE>
 __global__ void __launch_bounds__(TX * TY * (TZ / CZ), WPE)
 k_substep(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
@@ -365,91 +460,197 @@ k_substep(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles
         __syncthreads();
         absorb<T, 3, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
 
-        // forcing (held fixed over the step's substeps)
-        const G<T> *fs = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
-        if (fs[6] != T(0)) {
-            const G<T> *Ex = fs + FHEAD, *Ey = Ex + 2 * nx, *Ez = Ey + 2 * ny;
+    }
+    int gpos[CZ][3];
 #pragma unroll
-            for (int c = 0; c < CZ; c++) {
-                if (!inside[c]) continue;
-                const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz0 + c * ZS;
-                const T xr = Ex[2 * gx], xi = Ex[2 * gx + 1];
-                const T yr = Ey[2 * gy], yi = Ey[2 * gy + 1];
-                const T zr = Ez[2 * gz], zi = Ez[2 * gz + 1];
-                const T pr = xr * yr - xi * yi, pi = xr * yi + xi * yr;
-                const T cr = pr * zr - pi * zi, ci = pr * zi + pi * zr;
-#pragma unroll
-                for (int a = 0; a < 3; a++) C.R[c][1 + a] += fs[a] * cr + fs[3 + a] * ci;
-            }
-        }
+    for (int c = 0; c < CZ; c++) {
+        gpos[c][0] = x0 + lx;
+        gpos[c][1] = y0 + ly;
+        gpos[c][2] = z0 + lz0 + c * ZS;
+    }
+    finish<T, CZ, NT, SUB, DIAG, STORE>(C, r, te, K, dc, inside, gcell, gpos, out,
+                                          reinterpret_cast<double *>(&lds[1][0]), step, tid);
+}
 
-        const T bdt = K.bdt[SUB], brho = K.brho[SUB];
+// ------------------------------------------------------------------ pipelined variant
+//
+// Same arithmetic as k_substep, different staging: the halo box of each field is
+// copied HBM -> LDS by the direct-to-LDS loads of gfx950 (global_load_lds_dwordx4,
+// 16 bytes per lane, no registers involved) into a ring of three buffers, two
+// fields ahead of the one being differentiated, so about twice the bytes are in
+// flight per CU and no VGPRs hold staged data.  Completion is tracked with explicit
+// vmcnt waits before plain s_barriers (a full __syncthreads would wait for every
+// outstanding load, including the prefetches).  The box starts at x0-4 so that
+// each 16-byte vector holds whole, contiguous elements of one row; this needs
+// nx % (16 / sizeof(T)) == 0 and 16-byte aligned field arrays (checked on the host).
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gconst_void_t;
+
+// s_waitcnt that limits only vmcnt (gfx9 encoding: vmcnt in bits 3:0 and 15:14,
+// expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit counter");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// barrier for the ring: this wave's copies up to the limit have landed; all waves
+// have finished the previous pass
+template <int N>
+__device__ __forceinline__ void ring_barrier()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    wait_vmcnt<N>();
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <typename T, int NV, int NT, int EPL>
+__device__ __forceinline__ void ring_copy(const G<T> *src, T *buf, const uint32_t (&voff)[NV], int wave)
+{
+    const G<char> *base = (const G<char> *)src;
 #pragma unroll
-        for (int c = 0; c < CZ; c++) {
-            if (!inside[c]) continue;
+    for (int v = 0; v < NV; v++)
+        __builtin_amdgcn_global_load_lds((gconst_void_t *)(base + voff[v]),
+                                         (lds_void_t *)(buf + (v * NT + wave * 64) * EPL), 16, 0, 0);
+}
+
+template <typename T, int TX, int TY, int TZ, int CZ, int SUB, bool DIAG, bool STORE, int WPE, bool FIT>
+__global__ void __launch_bounds__(TX * TY * (TZ / CZ), WPE)
+k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
+{
+    constexpr int NT = TX * TY * (TZ / CZ);
+    constexpr int EPL = 16 / (int)sizeof(T);
+    constexpr int XW = TX + 8, YW = TY + 6, ZW = TZ + 6;
+    constexpr int VOL = XW * YW * ZW;
+    constexpr int NVEC = VOL / EPL;
+    constexpr int NV = (NVEC + NT - 1) / NT;
+    constexpr int BUF = NV * NT * EPL;
+    constexpr int SY = XW, SZ = XW * YW;
+    constexpr int ZS = TZ / CZ;
+    static_assert(XW % EPL == 0 && TX % EPL == 0, "rows must hold whole vectors");
+    static_assert(NT % 64 == 0, "whole waves");
+
+    __shared__ __align__(16) T lds[3][BUF];
+
+    const TileEnt te = tiles[blockIdx.x];
+    const RunDesc<T> &r = runs[te.run];
+    const int nx = r.nx, ny = r.ny, nz = r.nz;
+    const int x0 = te.xy & 0xffff, y0 = te.xy >> 16, z0 = te.z0;
+    const int par = (r.parity0 + step) & 1;
+    const int in_set = (SUB == 1) ? (par ^ 1) : par;
+    const int out_set = (SUB == 1) ? par : (par ^ 1);
+    const G<T> *in[NF];
+    G<T> *out[NF];
 #pragma unroll
-            for (int f = 0; f < NF; f++) {
-                T o;
-                if constexpr (SUB == 0) {
-                    o = C.v[c][f] + bdt * C.R[c][f];
-                } else {
-                    const T old = out[f][gcell[c]];
-                    o = C.v[c][f] + brho * (C.v[c][f] - old) + bdt * C.R[c][f];
-                }
-                out[f][gcell[c]] = o;
-            }
-        }
+    for (int f = 0; f < NF; f++) {
+        in[f] = (const G<T> *)r.buf[in_set][f];
+        out[f] = (G<T> *)r.buf[out_set][f];
     }
 
-    if constexpr (DIAG) {
-        // the diagnostic-only pass still needs the A centre values for its finiteness check
-        double acc[9];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz0 = tid / (TX * TY);
+
+    // byte offsets of this thread's vectors of the halo box (same for every field)
+    uint32_t voff[NV];
 #pragma unroll
-        for (int q = 0; q < 9; q++) acc[q] = 0.0;
-#pragma unroll
-        for (int c = 0; c < CZ; c++) {
-            if (!inside[c]) continue;
-            const double bx = C.Bd[c][0] + dc.bext[0], by = C.Bd[c][1] + dc.bext[1], bz = C.Bd[c][2] + dc.bext[2];
-            const double ux = (double)C.v[c][1], uy = (double)C.v[c][2], uz = (double)C.v[c][3];
-            const double u2 = ux * ux + uy * uy + uz * uz;
-            const double b2 = bx * bx + by * by + bz * bz;
-            acc[0] += b2;
-            acc[1] += u2;
-            acc[2] += exp((double)C.v[c][0]) * u2;
-            acc[3] += (double)C.v[c][0];
-            acc[4] += bx;
-            acc[5] += by;
-            acc[6] += bz;
-            acc[7] = fmax(acc[7], u2);
-            bool ok = true;
-#pragma unroll
-            for (int f = 0; f < NF; f++) ok = ok && finite_v(C.v[c][f]);
-            acc[8] += ok ? 0.0 : 1.0;
+    for (int v = 0; v < NV; v++) {
+        int qv = v * NT + tid;
+        if (qv >= NVEC) qv = NVEC - 1;  // padding lanes re-read a valid vector
+        const int q = qv * EPL;
+        const int bx = q % XW, by = (q / XW) % YW, bz = q / SZ;
+        int gx = x0 - 4 + bx, gy = y0 - 3 + by, gz = z0 - 3 + bz;
+        if constexpr (FIT) {  // the box spans at most one period per axis
+            gx += gx < 0 ? nx : (gx >= nx ? -nx : 0);
+            gy += gy < 0 ? ny : (gy >= ny ? -ny : 0);
+            gz += gz < 0 ? nz : (gz >= nz ? -nz : 0);
+        } else {
+            gx = wrapi(gx, nx);
+            gy = wrapi(gy, ny);
+            gz = wrapi(gz, nz);
         }
-        // wave reduction, then across waves through LDS (fixed order: deterministic)
-#pragma unroll
-        for (int q = 0; q < 9; q++) {
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const double w = __shfl_xor(acc[q], o, 64);
-                acc[q] = (q == 7) ? fmax(acc[q], w) : acc[q] + w;
-            }
-        }
-        constexpr int NW = NT / 64;
-        __syncthreads();
-        double *red = reinterpret_cast<double *>(&lds[1][0]);
-        const int wave = tid / 64, lane = tid % 64;
-        if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < 9; q++) red[wave * 9 + q] = acc[q];
-        }
-        __syncthreads();
-        if (tid < 9) {
-            double s = red[tid];
-            for (int w = 1; w < NW; w++) s = (tid == 7) ? fmax(s, red[w * 9 + tid]) : s + red[w * 9 + tid];
-            ((G<double> *)r.partials)[(size_t)te.tir * DIAGW + tid] = s;
-        }
+        voff[v] = (uint32_t)sizeof(T) * ((uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz));
     }
+
+    int cidx[CZ];
+    uint32_t gcell[CZ];
+    bool inside[CZ];
+    int gpos[CZ][3];
+#pragma unroll
+    for (int c = 0; c < CZ; c++) {
+        const int lz = lz0 + c * ZS;
+        cidx[c] = (lz + 3) * SZ + (ly + 3) * SY + (lx + 4);
+        gpos[c][0] = x0 + lx;
+        gpos[c][1] = y0 + ly;
+        gpos[c][2] = z0 + lz;
+        inside[c] = gpos[c][0] < nx && gpos[c][1] < ny && gpos[c][2] < nz;
+        gcell[c] = inside[c] ? (uint32_t)gpos[c][0] + (uint32_t)nx * ((uint32_t)gpos[c][1] + (uint32_t)ny * (uint32_t)gpos[c][2])
+                             : 0u;
+    }
+
+    Cells<T, CZ> C;
+#pragma unroll
+    for (int c = 0; c < CZ; c++) {
+#pragma unroll
+        for (int f = 0; f < NF; f++) C.R[c][f] = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; a++) { C.B[c][a] = T(0); C.J[c][a] = T(0); C.Bd[c][a] = 0.0; }
+        C.v[c][0] = in[0][gcell[c]];
+        C.v[c][1] = in[1][gcell[c]];
+        C.v[c][2] = in[2][gcell[c]];
+        C.v[c][3] = in[3][gcell[c]];
+    }
+    const Coef<T> &K = r.c;
+    const DCoef &dc = r.dc;
+    // the centre loads go out before any ring copy, so the wait for them does not
+    // also wait for the prefetched fields
+    __builtin_amdgcn_sched_barrier(0);
+
+    // fields pass in the order ln rho, A_x, A_y, A_z, u_x, u_y, u_z; field k of that
+    // order lives in ring buffer k % 3 and is requested two passes ahead
+    ring_copy<T, NV, NT, EPL>(in[0], lds[0], voff, wave);
+    ring_copy<T, NV, NT, EPL>(in[4], lds[1], voff, wave);
+
+    ring_barrier<NV>();
+    ring_copy<T, NV, NT, EPL>(in[5], lds[2], voff, wave);
+    absorb<T, 0, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+
+    ring_barrier<NV>();
+    ring_copy<T, NV, NT, EPL>(in[6], lds[0], voff, wave);
+    absorb<T, 4, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
+
+    if constexpr (STORE) {
+        ring_barrier<NV>();
+        ring_copy<T, NV, NT, EPL>(in[1], lds[1], voff, wave);
+        absorb<T, 5, SY, SZ, CZ, DIAG>(C, lds[2], cidx, K, dc);
+
+        ring_barrier<NV>();
+        ring_copy<T, NV, NT, EPL>(in[2], lds[2], voff, wave);
+        absorb<T, 6, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+
+        ring_barrier<NV>();
+        ring_copy<T, NV, NT, EPL>(in[3], lds[0], voff, wave);
+        absorb<T, 1, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
+
+        ring_barrier<NV>();
+        absorb<T, 2, SY, SZ, CZ, DIAG>(C, lds[2], cidx, K, dc);
+
+        ring_barrier<0>();
+        absorb<T, 3, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+    } else {
+        ring_barrier<NV>();
+        absorb<T, 5, SY, SZ, CZ, DIAG>(C, lds[2], cidx, K, dc);
+
+        ring_barrier<0>();
+        absorb<T, 6, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    finish<T, CZ, NT, SUB, DIAG, STORE>(C, r, te, K, dc, inside, gcell, gpos, out,
+                                          reinterpret_cast<double *>(&lds[1][0]), step, tid);
 }
 
 // Per-run reduction of the tile partials into one diagnostic record (one block per

@@ -14,8 +14,9 @@ namespace mhd {
 
 struct Shape {
     int tx, ty, tz, cz;
+    bool pipe;   // true: direct-to-LDS ring kernel (k_pipe); false: register-staged kernel (k_substep)
 };
-constexpr int NSHAPES = 6;
+constexpr int NSHAPES = 12;
 extern const Shape SHAPES[NSHAPES];
 
 // steps whose forcing blocks and diagnostic records are staged at once
@@ -33,6 +34,7 @@ struct mhd_ctx {
     size_t ncell = 0;
     hipStream_t stream = nullptr;
     int shape = 0;
+    bool fit = false;        // halo box spans at most one period per axis (cheap wrap)
     int ntiles = 0;
     int fstride = 0;
     bool owns = false;
@@ -66,7 +68,9 @@ namespace mhd {
 
 mhd_status check_params(const mhd_params *p);
 mhd_status check_forcing(const mhd_forcing &f);
-int default_shape(const mhd_params &p);
+int default_shape(const mhd_params &p, bool aligned = true);
+bool shape_eligible(const mhd_params &p, int shape, bool aligned);
+bool shape_fits(const mhd_params &p, int shape);
 int forcing_stride(const mhd_params &p);
 int run_ntiles(const mhd_params &p, int shape);
 void run_tiles(const mhd_params &p, int shape, int run, std::vector<TileEnt> &out);
@@ -84,8 +88,8 @@ template <typename T>
 void fill_desc(const mhd_ctx *c, RunDesc<T> &d, int parity0, int64_t step0, const T *forcing, double *records,
                double *partials, int first_tile);
 template <typename T>
-hipError_t launch_substep(int shape, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles, int step,
-                          hipStream_t st);
+hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles,
+                          int step, hipStream_t st);
 template <typename T>
 hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int step, hipStream_t st);
 

@@ -27,6 +27,7 @@ namespace mhd {
 struct Group {
     int prec = 8;
     int shape = 0;
+    bool fit = false;
     std::vector<mhd_ctx *> members;
     int ntiles = 0;
     TileEnt *d_tiles = nullptr;
@@ -98,15 +99,16 @@ struct MultiRunner {
         groups.clear();
         if (!stage_evt && hipEventCreateWithFlags(&stage_evt, hipEventDisableTiming) != hipSuccess)
             return fail(MHD_E_DEVICE, "hipEventCreate failed");
-        std::map<std::pair<int, int>, size_t> index;
+        std::map<std::tuple<int, int, bool>, size_t> index;
         for (mhd_ctx *c : runs) {
-            auto key = std::make_pair(c->p.precision, c->shape);
+            auto key = std::make_tuple(c->p.precision, c->shape, c->fit);
             auto it = index.find(key);
             if (it == index.end()) {
                 index[key] = groups.size();
                 Group g;
                 g.prec = c->p.precision;
                 g.shape = c->shape;
+                g.fit = c->fit;
                 groups.push_back(g);
                 it = index.find(key);
             }
@@ -133,10 +135,10 @@ struct MultiRunner {
     {
         const RunDesc<T> *d = (const RunDesc<T> *)g.d_descs;
         const int nr = (int)g.members.size();
-        hipError_t e = launch_substep<T>(g.shape, 0, d, g.d_tiles, g.ntiles, s, stream);
+        hipError_t e = launch_substep<T>(g.shape, g.fit, 0, d, g.d_tiles, g.ntiles, s, stream);
         if (e == hipSuccess) e = launch_finalize<T>(d, nr, s, stream);
-        if (e == hipSuccess) e = launch_substep<T>(g.shape, 1, d, g.d_tiles, g.ntiles, s, stream);
-        if (e == hipSuccess) e = launch_substep<T>(g.shape, 2, d, g.d_tiles, g.ntiles, s, stream);
+        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 1, d, g.d_tiles, g.ntiles, s, stream);
+        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 2, d, g.d_tiles, g.ntiles, s, stream);
         return e;
     }
 

@@ -99,7 +99,7 @@ def test_config1_32cubed_every_step(mhd, prec):
             assert abs(rec[k] - ref[k]) <= 1e-12 * abs(ref[k]) + 1e-300, (n, k, rec[k], ref[k])
 
 
-@pytest.mark.parametrize("shape", range(6))
+@pytest.mark.parametrize("shape", range(12))
 def test_every_tile_shape_ragged_grid_fp64(mhd, shape):
     rp = mi.RunParams(20, 18, 13, nu=4e-3, eta=6e-3, dt=1e-3, precision=8, bext=(0.01, 0.0, -0.02))
     st = mi.noise_state(rp, 5 + shape, 0.2, 0.2, 0.2)
@@ -110,7 +110,7 @@ def test_every_tile_shape_ragged_grid_fp64(mhd, shape):
         check_step(got[n], want[n], scales[n], rp, f"shape {shape} step {n + 1}")
 
 
-@pytest.mark.parametrize("shape", [0, 3, 5])
+@pytest.mark.parametrize("shape", [0, 3, 5, 6, 8, 9, 11])
 def test_tile_shapes_fp32(mhd, shape):
     rp = mi.RunParams(24, 20, 17, nu=4e-3, eta=6e-3, dt=1e-3, precision=4)
     st = mi.noise_state(rp, 7, 0.2, 0.2, 0.2, dtype=np.float32)
@@ -119,6 +119,19 @@ def test_tile_shapes_fp32(mhd, shape):
     want, scales = oracle_per_step(st, rp, recs)
     for n in range(2):
         check_step(got[n], want[n], scales[n], rp, f"fp32 shape {shape} step {n + 1}")
+
+
+@pytest.mark.parametrize("prec", [8, 4])
+@pytest.mark.parametrize("shape", range(6, 12))
+def test_ring_shapes_wrap_once(mhd, shape, prec):
+    """Ring kernels on a grid larger than their halo box (single-wrap offsets)."""
+    rp = mi.RunParams(48, 40, 32, nu=3e-3, eta=2e-3, dt=1e-3, precision=prec)
+    st = mi.noise_state(rp, 60 + shape, 0.2, 0.2, 0.2, dtype=_dtype(prec))
+    recs = mi.forcing_schedule(8, 2, 3.0, 0.05, 1.0)
+    got, _ = gpu_run(mhd, rp, st, recs, per_step=True, shape=shape)
+    want, scales = oracle_per_step(st, rp, recs)
+    for n in range(2):
+        check_step(got[n], want[n], scales[n], rp, f"ring shape {shape} fp{8 * prec} step {n + 1}")
 
 
 @pytest.mark.parametrize("n", [8, 9, 33])
