@@ -90,13 +90,15 @@ def test_config1_32cubed_every_step(mhd, prec):
         check_step(got[n], want[n], scales[n], rp, f"cfg1 fp{8 * prec} step {n + 1}")
     # diagnostics of the input state of every step, and of the final state
     assert len(diag) == 21
+    # (step 0 is the shared input; later FP32 states are the GPU's own FP32 trajectory,
+    # compared with the oracle's FP64 one at the FP32 bar)
     states = [st.astype(np.float64)] + want
     for n, rec in enumerate(diag):
-        ref = oracle.diag(states[n] if prec == 8 else
-                          (states[n] if n == 0 else got[n - 1].astype(np.float64)), rp)
+        ref = oracle.diag(states[n], rp)
+        tol = 1e-12 if (prec == 8 or n == 0) else 1e-5
         assert rec["step"] == n and abs(rec["t"] - n * rp.dt) < 1e-15
         for k in ("em", "ek", "urms", "brms", "umax"):
-            assert abs(rec[k] - ref[k]) <= 1e-12 * abs(ref[k]) + 1e-300, (n, k, rec[k], ref[k])
+            assert abs(rec[k] - ref[k]) <= tol * abs(ref[k]) + 1e-300, (n, k, rec[k], ref[k])
 
 
 @pytest.mark.parametrize("shape", range(12))
