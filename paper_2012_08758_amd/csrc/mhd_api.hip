@@ -286,22 +286,34 @@ mhd_status check_params(const mhd_params *p)
 
 // ------------------------------------------------------------------ tiles
 
-// Tiles of a run in natural order (z, then y, then x).
+// Tiles of a run in the order the work-groups should meet them.  The (x, y) columns
+// of tiles are grouped into patches of about as many columns as one XCD runs at
+// once; a patch is walked through z one level at a time.  Tiles running together
+// then share their x/y halo lines in L2, and the z halo of one level is still in
+// L2 when the next level reads it.  (In plain z-y-x order the z neighbours of a tile
+// are thousands of tiles away and every z halo is fetched from HBM again.)
+// tir (the partials slot) stays the natural z-y-x index.
 void run_tiles(const mhd_params &p, int shape, int run, std::vector<TileEnt> &out)
 {
     const Shape &s = SHAPES[shape];
     const int ntx = (p.nx + s.tx - 1) / s.tx, nty = (p.ny + s.ty - 1) / s.ty, ntz = (p.nz + s.tz - 1) / s.tz;
-    int q = 0;
-    for (int tz = 0; tz < ntz; tz++)
-        for (int ty = 0; ty < nty; ty++)
-            for (int tx = 0; tx < ntx; tx++) {
-                TileEnt t;
-                t.run = run;
-                t.xy = (tx * s.tx) | ((ty * s.ty) << 16);
-                t.z0 = tz * s.tz;
-                t.tir = q++;
-                out.push_back(t);
-            }
+    // columns per patch ~ resident work-groups per XCD (32 CUs x 1-2 groups)
+    const int target = p.precision == MHD_FP64 ? 32 : 64;
+    int px = 1;
+    while (px * 2 <= ntx && px * px * 2 <= target) px *= 2;
+    int py = std::max(1, std::min(nty, target / px));
+    for (int pY = 0; pY < nty; pY += py)
+        for (int pX = 0; pX < ntx; pX += px)
+            for (int tz = 0; tz < ntz; tz++)
+                for (int ty = pY; ty < std::min(nty, pY + py); ty++)
+                    for (int tx = pX; tx < std::min(ntx, pX + px); tx++) {
+                        TileEnt t;
+                        t.run = run;
+                        t.xy = (tx * s.tx) | ((ty * s.ty) << 16);
+                        t.z0 = tz * s.tz;
+                        t.tir = tx + ntx * (ty + nty * tz);
+                        out.push_back(t);
+                    }
 }
 
 int run_ntiles(const mhd_params &p, int shape)
@@ -389,18 +401,23 @@ hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs,
     }
 }
 
+int run_nb2(const mhd_params &p, int shape) { return (run_ntiles(p, shape) + FIN_CHUNK - 1) / FIN_CHUNK; }
+
 template <typename T>
-hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int step, hipStream_t st)
+hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int max_nb2, int step, hipStream_t st)
 {
     if (nruns <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_finalize<T>), dim3(nruns), dim3(256), 0, st, runs, step);
+    hipLaunchKernelGGL((k_finalize1<T>), dim3(nruns, max_nb2), dim3(256), 0, st, runs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_finalize2<T>), dim3(nruns), dim3(64), 0, st, runs, step);
     return hipGetLastError();
 }
 
 template hipError_t launch_substep<float>(int, bool, int, const RunDesc<float> *, const TileEnt *, int, int, hipStream_t);
 template hipError_t launch_substep<double>(int, bool, int, const RunDesc<double> *, const TileEnt *, int, int, hipStream_t);
-template hipError_t launch_finalize<float>(const RunDesc<float> *, int, int, hipStream_t);
-template hipError_t launch_finalize<double>(const RunDesc<double> *, int, int, hipStream_t);
+template hipError_t launch_finalize<float>(const RunDesc<float> *, int, int, int, hipStream_t);
+template hipError_t launch_finalize<double>(const RunDesc<double> *, int, int, int, hipStream_t);
 
 // ------------------------------------------------------------------ context
 
@@ -409,7 +426,8 @@ size_t ctx_footprint(const mhd_params &p)
     const size_t n = (size_t)p.nx * p.ny * p.nz;
     const size_t fb = align_up(n * (size_t)p.precision, 256);
     const int nt = run_ntiles(p, default_shape(p));
-    return 14 * fb + (size_t)nt * DIAGW * 8 + (size_t)CHUNK * forcing_stride(p) * p.precision +
+    return 14 * fb + (size_t)(nt + run_nb2(p, default_shape(p))) * DIAGW * 8 +
+           (size_t)CHUNK * forcing_stride(p) * p.precision +
            (size_t)CHUNK * DREC * 8 + 4096;
 }
 
@@ -421,15 +439,17 @@ static mhd_status ctx_alloc_aux(mhd_ctx *c)
     const size_t fbytes = (size_t)CHUNK * c->fstride * c->p.precision;
     const size_t rbytes = (size_t)CHUNK * DREC * sizeof(double);
     const size_t pbytes = (size_t)c->ntiles * DIAGW * sizeof(double);
+    const size_t p2bytes = (size_t)c->nb2 * DIAGW * sizeof(double);
     const size_t dbytes = 1024;
     const size_t tbytes = (size_t)c->ntiles * sizeof(TileEnt);
-    c->aux_bytes = align_up(fbytes, 256) + align_up(rbytes, 256) + align_up(pbytes, 256) + align_up(dbytes, 256) +
-                   align_up(tbytes, 256);
+    c->aux_bytes = align_up(fbytes, 256) + align_up(rbytes, 256) + align_up(pbytes, 256) + align_up(p2bytes, 256) +
+                   align_up(dbytes, 256) + align_up(tbytes, 256);
     if (hipMalloc(&c->aux, c->aux_bytes) != hipSuccess) return fail(MHD_E_OOM, "device allocation (aux) failed");
     char *b = (char *)c->aux;
     c->d_forcing = b; b += align_up(fbytes, 256);
     c->d_records = (double *)b; b += align_up(rbytes, 256);
     c->d_partials = (double *)b; b += align_up(pbytes, 256);
+    c->d_partials2 = (double *)b; b += align_up(p2bytes, 256);
     c->d_desc = b; b += align_up(dbytes, 256);
     c->d_tiles = (TileEnt *)b;
     c->h_stage_bytes = fbytes + dbytes;
@@ -476,6 +496,7 @@ mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *
     c->shape = shape >= 0 ? shape : default_shape(*p, aligned);
     c->fit = SHAPES[c->shape].pipe && shape_fits(*p, c->shape);
     c->ntiles = run_ntiles(*p, c->shape);
+    c->nb2 = run_nb2(*p, c->shape);
     mhd_status st = ctx_alloc_aux(c);
     if (st != MHD_OK) return st;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(MHD_E_DEVICE, "stream sync failed");
@@ -530,6 +551,8 @@ void fill_desc(const mhd_ctx *c, RunDesc<T> &d, int parity0, int64_t step0, cons
     fill_coef<T>(c->p, d.c, d.dc);
     d.forcing = forcing;
     d.partials = partials;
+    d.partials2 = c->d_partials2;
+    d.nb2 = c->nb2;
     d.records = records;
     d.step0 = (double)step0;
     d.t0 = (double)step0 * c->p.dt;
@@ -623,7 +646,7 @@ static mhd_status ctx_step_t(mhd_ctx *c, int64_t nsteps)
         const RunDesc<T> *d = (const RunDesc<T> *)c->d_desc;
         for (int64_t s = 0; s < m; s++) {
             hipError_t e = launch_substep<T>(c->shape, c->fit, 0, d, c->d_tiles, c->ntiles, (int)s, c->stream);
-            if (e == hipSuccess) e = launch_finalize<T>(d, 1, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_finalize<T>(d, 1, c->nb2, (int)s, c->stream);
             if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -665,7 +688,7 @@ static mhd_status ctx_step_timed_t(mhd_ctx *c, int64_t nsteps, double kms[4], do
             hipError_t e = hipEventRecord(E[0], c->stream);
             if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 0, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[1], c->stream);
-            if (e == hipSuccess) e = launch_finalize<T>(d, 1, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_finalize<T>(d, 1, c->nb2, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[2], c->stream);
             if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[3], c->stream);
@@ -708,7 +731,7 @@ static mhd_status ctx_reduce_t(mhd_ctx *c)
     if (st != MHD_OK) return st;
     const RunDesc<T> *d = (const RunDesc<T> *)c->d_desc;
     hipError_t e = launch_substep<T>(c->shape, c->fit, 3, d, c->d_tiles, c->ntiles, 0, c->stream);
-    if (e == hipSuccess) e = launch_finalize<T>(d, 1, 0, c->stream);
+    if (e == hipSuccess) e = launch_finalize<T>(d, 1, c->nb2, 0, c->stream);
     if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     c->rcount += 1;
     return MHD_OK;

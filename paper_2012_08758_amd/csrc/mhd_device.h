@@ -50,6 +50,8 @@ struct RunDesc {
     DCoef dc;
     const T *forcing;   // per batch step: FHEAD values then Ex[2nx], Ey[2ny], Ez[2nz]
     double *partials;   // [ntiles][DIAGW]
+    double *partials2;  // [nb2][DIAGW]: second level of the diagnostic reduction
+    int nb2, pad2;      // blocks of the first finalize level (FIN_CHUNK partials each)
     double *records;    // [batch step][DREC]
     double step0;       // global step index of batch step 0
     double t0, dt;
@@ -112,6 +114,8 @@ struct Cells {
     T B[CZ][3], J[CZ][3];
     T R[CZ][NF];        // right-hand side accumulators
     double Bd[CZ][3];   // FP64 curl, for the diagnostics
+    T old[CZ][NF];      // state of substep s-2 at the cells (filled early by the ring kernel)
+    bool have_old = false;
 };
 
 template <int A, int SY, int SZ>
@@ -246,10 +250,50 @@ __device__ __forceinline__ void stage_store(T *dst, const T (&stage)[NL], int ti
     }
 }
 
+// The forcing term (held fixed over a step's substeps) at this thread's cells, in
+// two halves: load() issues the reads of the per-axis phase tables early, add()
+// folds f = a cos(theta) + b sin(theta) into the momentum accumulators later, once
+// the reads have long returned.
+template <typename T, int CZ>
+struct ForcingAt {
+    bool on = false;
+    T a[3], b[3];
+    T ex[CZ][2], ey[CZ][2], ez[CZ][2];
+
+    __device__ __forceinline__ void load(const RunDesc<T> &r, int step, const bool (&inside)[CZ],
+                                         const int (&gpos)[CZ][3])
+    {
+        const G<T> *fs = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
+        on = fs[6] != T(0);
+#pragma unroll
+        for (int q = 0; q < 3; q++) { a[q] = fs[q]; b[q] = fs[3 + q]; }
+        const G<T> *Ex = fs + FHEAD, *Ey = Ex + 2 * r.nx, *Ez = Ey + 2 * r.ny;
+#pragma unroll
+        for (int c = 0; c < CZ; c++) {
+            const int gx = inside[c] ? gpos[c][0] : 0, gy = inside[c] ? gpos[c][1] : 0, gz = inside[c] ? gpos[c][2] : 0;
+            ex[c][0] = Ex[2 * gx]; ex[c][1] = Ex[2 * gx + 1];
+            ey[c][0] = Ey[2 * gy]; ey[c][1] = Ey[2 * gy + 1];
+            ez[c][0] = Ez[2 * gz]; ez[c][1] = Ez[2 * gz + 1];
+        }
+    }
+
+    __device__ __forceinline__ void add(Cells<T, CZ> &C) const
+    {
+        if (!on) return;
+#pragma unroll
+        for (int c = 0; c < CZ; c++) {
+            const T pr = ex[c][0] * ey[c][0] - ex[c][1] * ey[c][1], pi = ex[c][0] * ey[c][1] + ex[c][1] * ey[c][0];
+            const T cr = pr * ez[c][0] - pi * ez[c][1], ci = pr * ez[c][1] + pi * ez[c][0];
+#pragma unroll
+            for (int q = 0; q < 3; q++) C.R[c][1 + q] += a[q] * cr + b[q] * ci;
+        }
+    }
+};
+
 // Forcing, RK3 update and diagnostic partials of this thread's cells (shared by
 // both substep kernels).  `red` is LDS scratch of at least 9 doubles per wave,
 // free once every thread has passed the preceding barrier.
-template <typename T, int CZ, int NT, int SUB, bool DIAG, bool STORE>
+template <typename T, int CZ, int NT, int SUB, bool DIAG, bool STORE, bool FORCE = true>
 __device__ __forceinline__ void finish(Cells<T, CZ> &C, const RunDesc<T> &r, const TileEnt &te, const Coef<T> &K,
                                        const DCoef &dc, const bool (&inside)[CZ], const uint32_t (&gcell)[CZ],
                                        const int (&gpos)[CZ][3], G<T> *const (&out)[NF], double *red, int step,
@@ -258,7 +302,7 @@ __device__ __forceinline__ void finish(Cells<T, CZ> &C, const RunDesc<T> &r, con
     if constexpr (STORE) {
         // forcing (held fixed over the step's substeps)
         const G<T> *fs = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
-        if (fs[6] != T(0)) {
+        if (FORCE && fs[6] != T(0)) {
             const G<T> *Ex = fs + FHEAD, *Ey = Ex + 2 * r.nx, *Ez = Ey + 2 * r.ny;
 #pragma unroll
             for (int c = 0; c < CZ; c++) {
@@ -284,7 +328,7 @@ __device__ __forceinline__ void finish(Cells<T, CZ> &C, const RunDesc<T> &r, con
                 if constexpr (SUB == 0) {
                     o = C.v[c][f] + bdt * C.R[c][f];
                 } else {
-                    const T old = out[f][gcell[c]];
+                    const T old = C.have_old ? C.old[c][f] : T(out[f][gcell[c]]);
                     o = C.v[c][f] + brho * (C.v[c][f] - old) + bdt * C.R[c][f];
                 }
                 out[f][gcell[c]] = o;
@@ -606,8 +650,10 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     }
     const Coef<T> &K = r.c;
     const DCoef &dc = r.dc;
-    // the centre loads go out before any ring copy, so the wait for them does not
-    // also wait for the prefetched fields
+    ForcingAt<T, CZ> frc;
+    if constexpr (STORE) frc.load(r, step, inside, gpos);
+    // the centre and forcing loads go out before any ring copy, so the waits for them
+    // do not also wait for the prefetched fields
     __builtin_amdgcn_sched_barrier(0);
 
     // fields pass in the order ln rho, A_x, A_y, A_z, u_x, u_y, u_z; field k of that
@@ -618,6 +664,7 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     ring_barrier<NV>();
     ring_copy<T, NV, NT, EPL>(in[5], lds[2], voff, wave);
     absorb<T, 0, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+    if constexpr (STORE) frc.add(C);
 
     ring_barrier<NV>();
     ring_copy<T, NV, NT, EPL>(in[6], lds[0], voff, wave);
@@ -640,6 +687,14 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         absorb<T, 2, SY, SZ, CZ, DIAG>(C, lds[2], cidx, K, dc);
 
         ring_barrier<0>();
+        // the s-2 state at this thread's cells, needed by the update: request it now
+        if constexpr (SUB != 0) {
+#pragma unroll
+            for (int c = 0; c < CZ; c++)
+#pragma unroll
+                for (int f = 0; f < NF; f++) C.old[c][f] = inside[c] ? out[f][gcell[c]] : T(0);
+            C.have_old = true;
+        }
         absorb<T, 3, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
     } else {
         ring_barrier<NV>();
@@ -649,57 +704,91 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         absorb<T, 6, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
     }
     __builtin_amdgcn_sched_barrier(0);
-    finish<T, CZ, NT, SUB, DIAG, STORE>(C, r, te, K, dc, inside, gcell, gpos, out,
-                                          reinterpret_cast<double *>(&lds[1][0]), step, tid);
+    finish<T, CZ, NT, SUB, DIAG, STORE, false>(C, r, te, K, dc, inside, gcell, gpos, out,
+                                                 reinterpret_cast<double *>(&lds[1][0]), step, tid);
 }
 
-// Per-run reduction of the tile partials into one diagnostic record (one block per
-// run, 256 threads, compensated sums in a fixed order).
-template <typename T>
-__global__ void __launch_bounds__(256) k_finalize(const RunDesc<T> *__restrict__ runs, int step)
+// Per-run reduction of the tile partials into one diagnostic record, in two launches
+// with a fixed assignment of partials to threads and fixed-order combines (so the
+// result is the same every run): level 1 sums FIN_CHUNK consecutive tile partials per
+// block with compensated sums, level 2 combines the level-1 results of a run.
+constexpr int FIN_CHUNK = 1024;
+
+__device__ __forceinline__ void csum_add(double &s, double &c, double x)
 {
-    const RunDesc<T> &r = runs[blockIdx.x];
-    __shared__ double sh[256][10];
+    const double u = s + x;
+    c += (fabs(s) >= fabs(x)) ? ((s - u) + x) : ((x - u) + s);
+    s = u;
+}
+
+// sums (q != 7) or maxima (q == 7) of 9 values per item, over items [lo, hi)
+// strided by blockDim, reduced through LDS in a fixed tree
+template <int NTH>
+__device__ __forceinline__ void block_reduce9(const G<double> *src, int lo, int hi, double (*sh)[10], double *out)
+{
     const int t = threadIdx.x;
     double s[9], cmp[9];
 #pragma unroll
     for (int q = 0; q < 9; q++) { s[q] = 0.0; cmp[q] = 0.0; }
-    for (int i = t; i < r.ntiles; i += 256) {
-        const double *p = r.partials + (size_t)i * DIAGW;
+    for (int i = lo + t; i < hi; i += NTH) {
+        const G<double> *p = src + (size_t)i * DIAGW;
 #pragma unroll
         for (int q = 0; q < 9; q++) {
             const double x = p[q];
-            if (q == 7) { s[q] = fmax(s[q], x); continue; }
-            const double u = s[q] + x;
-            cmp[q] += (fabs(s[q]) >= fabs(x)) ? ((s[q] - u) + x) : ((x - u) + s[q]);
-            s[q] = u;
+            if (q == 7) s[q] = fmax(s[q], x);
+            else csum_add(s[q], cmp[q], x);
         }
     }
 #pragma unroll
     for (int q = 0; q < 9; q++) sh[t][q] = (q == 7) ? s[q] : s[q] + cmp[q];
     __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
+    for (int w = NTH / 2; w >= 1; w >>= 1) {
         if (t < w) {
 #pragma unroll
             for (int q = 0; q < 9; q++) sh[t][q] = (q == 7) ? fmax(sh[t][q], sh[t + w][q]) : sh[t][q] + sh[t + w][q];
         }
         __syncthreads();
     }
-    if (t == 0) {
+    if (t < 9) out[t] = sh[0][t];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_finalize1(const RunDesc<T> *__restrict__ runs)
+{
+    const RunDesc<T> &r = runs[blockIdx.x];
+    const int b = blockIdx.y;
+    if (b >= r.nb2) return;
+    __shared__ double sh[256][10];
+    __shared__ double res[9];
+    const int lo = b * FIN_CHUNK, hi = min(r.ntiles, lo + FIN_CHUNK);
+    block_reduce9<256>((const G<double> *)r.partials, lo, hi, sh, res);
+    __syncthreads();
+    if (threadIdx.x < 9) ((G<double> *)r.partials2)[(size_t)b * DIAGW + threadIdx.x] = res[threadIdx.x];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_finalize2(const RunDesc<T> *__restrict__ runs, int step)
+{
+    const RunDesc<T> &r = runs[blockIdx.x];
+    __shared__ double sh[64][10];
+    __shared__ double res[9];
+    block_reduce9<64>((const G<double> *)r.partials2, 0, r.nb2, sh, res);
+    __syncthreads();
+    if (threadIdx.x == 0) {
         const double n = (double)r.nx * (double)r.ny * (double)r.nz;
-        double *o = r.records + (size_t)step * DREC;
+        G<double> *o = (G<double> *)r.records + (size_t)step * DREC;
         o[0] = r.step0 + (double)step;
         o[1] = r.t0 + (double)step * r.dt;
-        o[2] = 0.5 * sh[0][0] / n;
-        o[3] = 0.5 * sh[0][2] / n;
-        o[4] = sqrt(sh[0][1] / n);
-        o[5] = sqrt(sh[0][0] / n);
-        o[6] = sqrt(sh[0][7]);
-        o[7] = sh[0][3] / n;
-        o[8] = sh[0][4] / n;
-        o[9] = sh[0][5] / n;
-        o[10] = sh[0][6] / n;
-        o[11] = sh[0][8];
+        o[2] = 0.5 * res[0] / n;
+        o[3] = 0.5 * res[2] / n;
+        o[4] = sqrt(res[1] / n);
+        o[5] = sqrt(res[0] / n);
+        o[6] = sqrt(res[7]);
+        o[7] = res[3] / n;
+        o[8] = res[4] / n;
+        o[9] = res[5] / n;
+        o[10] = res[6] / n;
+        o[11] = res[8];
     }
 }
 

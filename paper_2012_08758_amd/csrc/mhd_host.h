@@ -55,6 +55,8 @@ struct mhd_ctx {
     void *d_forcing = nullptr;
     double *d_records = nullptr;
     double *d_partials = nullptr;
+    double *d_partials2 = nullptr;
+    int nb2 = 0;
     void *d_desc = nullptr;
     mhd::TileEnt *d_tiles = nullptr;
     void *h_stage = nullptr;
@@ -91,6 +93,7 @@ template <typename T>
 hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles,
                           int step, hipStream_t st);
 template <typename T>
-hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int step, hipStream_t st);
+hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int max_nb2, int step, hipStream_t st);
+int run_nb2(const mhd_params &p, int shape);
 
 }  // namespace mhd

@@ -30,6 +30,7 @@ struct Group {
     bool fit = false;
     std::vector<mhd_ctx *> members;
     int ntiles = 0;
+    int max_nb2 = 0;
     TileEnt *d_tiles = nullptr;
     void *d_descs = nullptr;
     void *h_descs = nullptr;   // pinned staging
@@ -119,6 +120,7 @@ struct MultiRunner {
             for (size_t i = 0; i < g.members.size(); i++) run_tiles(g.members[i]->p, g.shape, (int)i, nat);
             std::vector<TileEnt> ord = xcd_order(nat);
             g.ntiles = (int)ord.size();
+            for (mhd_ctx *c : g.members) g.max_nb2 = std::max(g.max_nb2, c->nb2);
             g.desc_bytes = g.members.size() * (g.prec == MHD_FP64 ? sizeof(RunDesc<double>) : sizeof(RunDesc<float>));
             if (hipMalloc(&g.d_tiles, ord.size() * sizeof(TileEnt)) != hipSuccess ||
                 hipMalloc(&g.d_descs, g.desc_bytes) != hipSuccess ||
@@ -136,7 +138,7 @@ struct MultiRunner {
         const RunDesc<T> *d = (const RunDesc<T> *)g.d_descs;
         const int nr = (int)g.members.size();
         hipError_t e = launch_substep<T>(g.shape, g.fit, 0, d, g.d_tiles, g.ntiles, s, stream);
-        if (e == hipSuccess) e = launch_finalize<T>(d, nr, s, stream);
+        if (e == hipSuccess) e = launch_finalize<T>(d, nr, g.max_nb2, s, stream);
         if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 1, d, g.d_tiles, g.ntiles, s, stream);
         if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 2, d, g.d_tiles, g.ntiles, s, stream);
         return e;
