@@ -96,10 +96,6 @@ int default_shape(const mhd_params &p, bool aligned)
 
 // ------------------------------------------------------------------ coefficients
 
-// Sixth-order central weights (exact for polynomials of degree 6 / 7):
-// first derivative, offsets 1..3; second derivative, offsets 0..3.
-static const double W1[3] = {3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0};
-static const double W2[4] = {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0};
 // Williamson (1980) third-order 2N Runge-Kutta
 static const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 static const double RK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
@@ -109,15 +105,12 @@ static void fill_coef(const mhd_params &p, Coef<T> &c, DCoef &dc)
 {
     const double h[3] = {p.lx / p.nx, p.ly / p.ny, p.lz / p.nz};
     for (int a = 0; a < 3; a++) {
-        for (int m = 0; m < 3; m++) {
-            c.d1[a][m] = (T)(W1[m] / h[a]);
-            dc.d1[a][m] = W1[m] / h[a];
-        }
-        for (int m = 0; m < 4; m++) c.d2[a][m] = (T)(W2[m] / (h[a] * h[a]));
+        c.ih1[a] = (T)(1.0 / h[a]);
+        dc.ih1[a] = 1.0 / h[a];
+        c.ih2[a] = (T)(1.0 / (h[a] * h[a]));
     }
     const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
-    for (int q = 0; q < 3; q++)
-        for (int m = 0; m < 3; m++) c.dm[q][m] = (T)(W2[m + 1] / (4.0 * h[pa[q]] * h[pb[q]]));
+    for (int q = 0; q < 3; q++) c.ihm[q] = (T)(1.0 / (4.0 * h[pa[q]] * h[pb[q]]));
     c.cs2 = (T)(p.cs * p.cs);
     c.nu = (T)p.nu;
     c.nu3 = (T)(p.nu / 3.0);

@@ -25,20 +25,47 @@ constexpr int DIAGW = 10;  // per-tile partials: |B|^2, |u|^2, rho|u|^2, lnrho, 
 constexpr int DREC = 12;   // record: step, t, em, ek, urms, brms, umax, <lnrho>, <Bx>, <By>, <Bz>, nonfinite
 constexpr int FHEAD = 8;   // forcing block head: a[3], b[3], on, spare
 
+// Sixth-order central weights (exact for polynomials of degree 6 / 7): first
+// derivative, offsets 1..3; second derivative, offsets 0..3.  The kernels take
+// them as compile-time constants (materialised by scalar moves, never loaded) and
+// scale each derivative by the run's inverse spacing.
+constexpr double W1_1 = 3.0 / 4.0, W1_2 = -3.0 / 20.0, W1_3 = 1.0 / 60.0;
+constexpr double W2_0 = -49.0 / 18.0, W2_1 = 3.0 / 2.0, W2_2 = -3.0 / 20.0, W2_3 = 1.0 / 90.0;
+
 template <typename T>
 struct Coef {
-    T d1[3][3];   // first derivative: weight of offset m+1, divided by h_axis
-    T d2[3][4];   // second derivative: weight of offset m (m = 0 centre), divided by h_axis^2
-    T dm[3][3];   // mixed derivative, pair 0 = xy, 1 = xz, 2 = yz: weight of diagonal offset m+1 / (4 h_a h_b)
+    T ih1[3];     // 1 / h_axis
+    T ih2[3];     // 1 / h_axis^2
+    T ihm[3];     // 1 / (4 h_a h_b), pair 0 = xy, 1 = xz, 2 = yz
     T cs2, nu, nu3, nu2_3, eta;
     T bext[3];
     T bdt[3];     // beta_s * dt
     T brho[3];    // beta_s * alpha_s / beta_{s-1} (0 for s = 0)
 };
 
-struct DCoef {      // FP64 copy of the curl weights, for diagnostics of FP32 runs
-    double d1[3][3];
+struct DCoef {      // FP64 inverse spacings and mean field, for diagnostics of FP32 runs
+    double ih1[3];
     double bext[3];
+};
+
+// The coefficients that the passes use, read once per work-group and held in scalar
+// registers for the whole kernel.  Without the pin the compiler re-reads them from
+// memory inside every pass, and each such scalar read must be waited for with the
+// counter that also tracks the pass's LDS reads, which serialises the pass.
+template <typename T>
+struct KRegs {
+    T ih1[3], ih2[3], ihm[3];
+    T cs2, nu, nu3, nu2_3, eta;
+
+    __device__ __forceinline__ void load(const Coef<T> &c)
+    {
+#pragma unroll
+        for (int a = 0; a < 3; a++) { ih1[a] = c.ih1[a]; ih2[a] = c.ih2[a]; ihm[a] = c.ihm[a]; }
+        cs2 = c.cs2; nu = c.nu; nu3 = c.nu3; nu2_3 = c.nu2_3; eta = c.eta;
+#pragma unroll
+        for (int a = 0; a < 3; a++) asm volatile("" : "+s"(ih1[a]), "+s"(ih2[a]), "+s"(ihm[a]));
+        asm volatile("" : "+s"(cs2), "+s"(nu), "+s"(nu3), "+s"(nu2_3), "+s"(eta));
+    }
 };
 
 template <typename T>
@@ -65,37 +92,34 @@ struct TileEnt {
 };
 
 template <typename T>
-__device__ __forceinline__ T sd1(const T *s, int st, const T *w)
+__device__ __forceinline__ T sd1(const T *s, int st, T ih)
 {
-    return w[0] * (s[st] - s[-st]) + w[1] * (s[2 * st] - s[-2 * st]) + w[2] * (s[3 * st] - s[-3 * st]);
+    return ih * (T(W1_1) * (s[st] - s[-st]) + T(W1_2) * (s[2 * st] - s[-2 * st]) + T(W1_3) * (s[3 * st] - s[-3 * st]));
 }
 
 template <typename T>
-__device__ __forceinline__ T sd2(const T *s, int st, const T *w)
+__device__ __forceinline__ T sd2(const T *s, int st, T ih2)
 {
-    return w[0] * s[0] + w[1] * (s[st] + s[-st]) + w[2] * (s[2 * st] + s[-2 * st]) +
-           w[3] * (s[3 * st] + s[-3 * st]);
+    return ih2 * (T(W2_0) * s[0] + T(W2_1) * (s[st] + s[-st]) + T(W2_2) * (s[2 * st] + s[-2 * st]) +
+                  T(W2_3) * (s[3 * st] + s[-3 * st]));
 }
 
 // d_a d_b from the (a+b) and (a-b) diagonals
 template <typename T>
-__device__ __forceinline__ T sdm(const T *s, int sa, int sb, const T *w)
+__device__ __forceinline__ T sdm(const T *s, int sa, int sb, T ihm)
 {
     const int p = sa + sb, q = sa - sb;
-    return w[0] * ((s[p] + s[-p]) - (s[q] + s[-q])) +
-           w[1] * ((s[2 * p] + s[-2 * p]) - (s[2 * q] + s[-2 * q])) +
-           w[2] * ((s[3 * p] + s[-3 * p]) - (s[3 * q] + s[-3 * q]));
+    return ihm * (T(W2_1) * ((s[p] + s[-p]) - (s[q] + s[-q])) +
+                  T(W2_2) * ((s[2 * p] + s[-2 * p]) - (s[2 * q] + s[-2 * q])) +
+                  T(W2_3) * ((s[3 * p] + s[-3 * p]) - (s[3 * q] + s[-3 * q])));
 }
 
-__device__ __forceinline__ double sd1d(const float *s, int st, const double *w)
+__device__ __forceinline__ double sd1d(const float *s, int st, double ih)
 {
-    return w[0] * ((double)s[st] - (double)s[-st]) + w[1] * ((double)s[2 * st] - (double)s[-2 * st]) +
-           w[2] * ((double)s[3 * st] - (double)s[-3 * st]);
+    return ih * (W1_1 * ((double)s[st] - (double)s[-st]) + W1_2 * ((double)s[2 * st] - (double)s[-2 * st]) +
+                 W1_3 * ((double)s[3 * st] - (double)s[-3 * st]));
 }
-__device__ __forceinline__ double sd1d(const double *s, int st, const double *w)
-{
-    return w[0] * (s[st] - s[-st]) + w[1] * (s[2 * st] - s[-2 * st]) + w[2] * (s[3 * st] - s[-3 * st]);
-}
+__device__ __forceinline__ double sd1d(const double *s, int st, double ih) { return sd1(s, st, ih); }
 
 __device__ __forceinline__ bool finite_v(float v) { return __builtin_isfinite(v); }
 __device__ __forceinline__ bool finite_v(double v) { return __builtin_isfinite(v); }
@@ -147,7 +171,7 @@ __device__ __forceinline__ void pin(Cells<T, CZ> &C)
 // Fold the derivatives of field F at this thread's cells into the accumulators.
 // Fields pass in the order ln rho, A_x, A_y, A_z, u_x, u_y, u_z.
 template <typename T, int F, int SY, int SZ, int CZ, bool DIAG>
-__device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&cidx)[CZ], const Coef<T> &K,
+__device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&cidx)[CZ], const KRegs<T> &K,
                                        const DCoef &dc)
 {
     constexpr bool IS_F64 = sizeof(T) == 8;
@@ -156,9 +180,9 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
     for (int c = 0; c < CZ; c++) {
         const T *s = S + cidx[c];
         if constexpr (F == 0) {
-            C.g[c][0] = sd1(s, s0, K.d1[0]);
-            C.g[c][1] = sd1(s, s1, K.d1[1]);
-            C.g[c][2] = sd1(s, s2, K.d1[2]);
+            C.g[c][0] = sd1(s, s0, K.ih1[0]);
+            C.g[c][1] = sd1(s, s1, K.ih1[1]);
+            C.g[c][2] = sd1(s, s2, K.ih1[2]);
             C.R[c][0] -= C.v[c][1] * C.g[c][0] + C.v[c][2] * C.g[c][1] + C.v[c][3] * C.g[c][2];
             C.R[c][1] -= K.cs2 * C.g[c][0];
             C.R[c][2] -= K.cs2 * C.g[c][1];
@@ -168,18 +192,18 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
             constexpr int b1 = (m + 1) % 3, b2 = (m + 2) % 3;  // the other two axes, cyclic
             constexpr int st1 = Stride<b1, SY, SZ>::v, st2 = Stride<b2, SY, SZ>::v, stm = Stride<m, SY, SZ>::v;
             C.v[c][F] = s[0];
-            const T d2m = sd2(s, stm, K.d2[m]);
-            const T d21 = sd2(s, st1, K.d2[b1]);
-            const T d22 = sd2(s, st2, K.d2[b2]);
+            const T d2m = sd2(s, stm, K.ih2[m]);
+            const T d21 = sd2(s, st1, K.ih2[b1]);
+            const T d22 = sd2(s, st2, K.ih2[b2]);
             C.R[c][F] += K.eta * (d2m + d21 + d22);
             // j_m = sum_{b != m} (d_m d_b A_b - d_b d_b A_m): the second part here
             C.J[c][m] -= d21 + d22;
             // j_b += d_b d_m A_m for b != m
-            C.J[c][b1] += sdm(s, st1, stm, K.dm[Pair<b1, m>::v]);
-            C.J[c][b2] += sdm(s, st2, stm, K.dm[Pair<b2, m>::v]);
+            C.J[c][b1] += sdm(s, st1, stm, K.ihm[Pair<b1, m>::v]);
+            C.J[c][b2] += sdm(s, st2, stm, K.ihm[Pair<b2, m>::v]);
             // B = curl A: A_m enters B_{b1} with + d_{b2} A_m and B_{b2} with - d_{b1} A_m
-            const T e1 = sd1(s, st1, K.d1[b1]);
-            const T e2 = sd1(s, st2, K.d1[b2]);
+            const T e1 = sd1(s, st1, K.ih1[b1]);
+            const T e2 = sd1(s, st2, K.ih1[b2]);
             C.B[c][b1] += e2;
             C.B[c][b2] -= e1;
             if constexpr (DIAG) {
@@ -187,15 +211,12 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
                     C.Bd[c][b1] += (double)e2;
                     C.Bd[c][b2] -= (double)e1;
                 } else {
-                    C.Bd[c][b1] += sd1d(s, st2, dc.d1[b2]);
-                    C.Bd[c][b2] -= sd1d(s, st1, dc.d1[b1]);
+                    C.Bd[c][b1] += sd1d(s, st2, dc.ih1[b2]);
+                    C.Bd[c][b2] -= sd1d(s, st1, dc.ih1[b1]);
                 }
             }
             if constexpr (F == 6) {
-                // A complete: Lorentz force and induction
-                C.B[c][0] += K.bext[0];
-                C.B[c][1] += K.bext[1];
-                C.B[c][2] += K.bext[2];
+                // A complete (B started from the imposed field): Lorentz force and induction
                 const T rinv = exp(-C.v[c][0]);
                 const T *Bv = C.B[c], *Jv = C.J[c], *u = &C.v[c][1];
                 C.R[c][1] += rinv * (Jv[1] * Bv[2] - Jv[2] * Bv[1]);
@@ -210,11 +231,11 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
             constexpr int b1 = (m + 1) % 3, b2 = (m + 2) % 3;
             constexpr int st1 = Stride<b1, SY, SZ>::v, st2 = Stride<b2, SY, SZ>::v, stm = Stride<m, SY, SZ>::v;
             T du[3];
-            du[m] = sd1(s, stm, K.d1[m]);
-            du[b1] = sd1(s, st1, K.d1[b1]);
-            du[b2] = sd1(s, st2, K.d1[b2]);
-            const T d2m = sd2(s, stm, K.d2[m]);
-            const T lap = d2m + sd2(s, st1, K.d2[b1]) + sd2(s, st2, K.d2[b2]);
+            du[m] = sd1(s, stm, K.ih1[m]);
+            du[b1] = sd1(s, st1, K.ih1[b1]);
+            du[b2] = sd1(s, st2, K.ih1[b2]);
+            const T d2m = sd2(s, stm, K.ih2[m]);
+            const T lap = d2m + sd2(s, st1, K.ih2[b1]) + sd2(s, st2, K.ih2[b2]);
             const T *g = C.g[c], *u = &C.v[c][1];
             // viscous: nu lap u_m + nu/3 d_m d_m u_m; advection; strain row m
             T rm = K.nu * lap + K.nu3 * d2m;
@@ -226,8 +247,8 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
 #pragma unroll
             for (int a = 0; a < 3; a++) C.R[c][1 + a] += K.nu * du[a] * g[m] - K.nu2_3 * du[m] * g[a];
             // grad div u: d_a d_m u_m for a != m
-            C.R[c][1 + b1] += K.nu3 * sdm(s, st1, stm, K.dm[Pair<b1, m>::v]);
-            C.R[c][1 + b2] += K.nu3 * sdm(s, st2, stm, K.dm[Pair<b2, m>::v]);
+            C.R[c][1 + b1] += K.nu3 * sdm(s, st1, stm, K.ihm[Pair<b1, m>::v]);
+            C.R[c][1 + b2] += K.nu3 * sdm(s, st2, stm, K.ihm[Pair<b2, m>::v]);
         }
     }
     pin(C);
@@ -447,7 +468,7 @@ k_substep(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles
 #pragma unroll
         for (int f = 0; f < NF; f++) C.R[c][f] = T(0);
 #pragma unroll
-        for (int a = 0; a < 3; a++) { C.B[c][a] = T(0); C.J[c][a] = T(0); C.Bd[c][a] = 0.0; }
+        for (int a = 0; a < 3; a++) { C.B[c][a] = r.c.bext[a]; C.J[c][a] = T(0); C.Bd[c][a] = 0.0; }
         // u and ln rho at the cell are needed by every pass: read them first
         C.v[c][0] = in[0][gcell[c]];
         C.v[c][1] = in[1][gcell[c]];
@@ -455,7 +476,8 @@ k_substep(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles
         C.v[c][3] = in[3][gcell[c]];
     }
 
-    const Coef<T> &K = r.c;
+    KRegs<T> K;
+    K.load(r.c);
     const DCoef &dc = r.dc;
     T stage[NL];
 
@@ -512,7 +534,7 @@ k_substep(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles
         gpos[c][1] = y0 + ly;
         gpos[c][2] = z0 + lz0 + c * ZS;
     }
-    finish<T, CZ, NT, SUB, DIAG, STORE>(C, r, te, K, dc, inside, gcell, gpos, out,
+    finish<T, CZ, NT, SUB, DIAG, STORE>(C, r, te, r.c, dc, inside, gcell, gpos, out,
                                           reinterpret_cast<double *>(&lds[1][0]), step, tid);
 }
 
@@ -642,13 +664,14 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
 #pragma unroll
         for (int f = 0; f < NF; f++) C.R[c][f] = T(0);
 #pragma unroll
-        for (int a = 0; a < 3; a++) { C.B[c][a] = T(0); C.J[c][a] = T(0); C.Bd[c][a] = 0.0; }
+        for (int a = 0; a < 3; a++) { C.B[c][a] = r.c.bext[a]; C.J[c][a] = T(0); C.Bd[c][a] = 0.0; }
         C.v[c][0] = in[0][gcell[c]];
         C.v[c][1] = in[1][gcell[c]];
         C.v[c][2] = in[2][gcell[c]];
         C.v[c][3] = in[3][gcell[c]];
     }
-    const Coef<T> &K = r.c;
+    KRegs<T> K;
+    K.load(r.c);
     const DCoef &dc = r.dc;
     ForcingAt<T, CZ> frc;
     if constexpr (STORE) frc.load(r, step, inside, gpos);
@@ -704,7 +727,7 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         absorb<T, 6, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
     }
     __builtin_amdgcn_sched_barrier(0);
-    finish<T, CZ, NT, SUB, DIAG, STORE, false>(C, r, te, K, dc, inside, gcell, gpos, out,
+    finish<T, CZ, NT, SUB, DIAG, STORE, false>(C, r, te, r.c, dc, inside, gcell, gpos, out,
                                                  reinterpret_cast<double *>(&lds[1][0]), step, tid);
 }
 
