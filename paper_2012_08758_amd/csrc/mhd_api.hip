@@ -87,8 +87,10 @@ int default_shape(const mhd_params &p, bool aligned)
         if (it != g_tuned.end()) want = it->second;
     }
     if (want < 0) {
+        // measured at 512^3: 16x8x8/2 is the fastest FP64 ring shape, 32x4x4/1 the
+        // fastest FP32 one; small grids want the small tile (more work-groups)
         const double n = (double)p.nx * p.ny * p.nz;
-        want = n <= 64.0 * 64 * 64 ? 8 : 6;
+        want = n <= 64.0 * 64 * 64 ? 8 : (p.precision == MHD_FP64 ? 9 : 10);
     }
     if (!shape_eligible(p, want, aligned)) want = SHAPES[want].pipe ? want - 6 : want;
     return want;
@@ -214,12 +216,11 @@ mhd_status check_forcing(const mhd_forcing &f)
 template <typename T>
 static void forcing_block(const mhd_params &p, const mhd_forcing &f, T *blk)
 {
+    constexpr int W = FSLOT<T>;
     for (int i = 0; i < FHEAD; i++) blk[i] = (T)0;
-    T *Ex = blk + FHEAD, *Ey = Ex + 2 * p.nx, *Ez = Ey + 2 * p.ny;
-    if (f.f0 == 0.0) {
-        for (int i = 0; i < 2 * (p.nx + p.ny + p.nz); i++) Ex[i] = (T)0;
-        return;
-    }
+    T *Ex = blk + FHEAD, *Ey = Ex + W * p.nx, *Ez = Ey + W * p.ny;
+    for (int i = 0; i < W * (p.nx + p.ny + p.nz); i++) Ex[i] = (T)0;
+    if (f.f0 == 0.0) return;
     const double L[3] = {p.lx, p.ly, p.lz};
     double K[3];
     for (int a = 0; a < 3; a++) K[a] = 2.0 * M_PI * f.k[a] / L[a];
@@ -245,15 +246,16 @@ static void forcing_block(const mhd_params &p, const mhd_forcing &f, T *blk)
             int64_t m = ((int64_t)f.k[a] * i) % na;
             if (m < 0) m += na;
             const double th = 2.0 * M_PI * (double)m / (double)na + (a == 0 ? f.phi : 0.0);
-            tab[a][2 * i] = (T)std::cos(th);
-            tab[a][2 * i + 1] = (T)std::sin(th);
+            tab[a][W * i] = (T)std::cos(th);
+            tab[a][W * i + 1] = (T)std::sin(th);
         }
     }
 }
 
 int forcing_stride(const mhd_params &p)
 {
-    int s = FHEAD + 2 * (p.nx + p.ny + p.nz);
+    // head, then one 16-byte slot per index of each axis; blocks start 64-byte aligned
+    int s = FHEAD + (16 / p.precision) * (p.nx + p.ny + p.nz);
     return (s + 7) & ~7;
 }
 
@@ -307,6 +309,39 @@ void run_tiles(const mhd_params &p, int shape, int run, std::vector<TileEnt> &ou
                         t.tir = tx + ntx * (ty + nty * tz);
                         out.push_back(t);
                     }
+}
+
+// Offset of the ring kernel's tile grid in x.  A halo-box row spans TX + 8 values;
+// where it falls on 128-byte lines decides how many lines the row costs, and line
+// requests in flight per CU are what bound the staging rate.  Choose, among offsets
+// that keep 16-byte vectors aligned, the one that touches the fewest lines over a
+// row of tiles (rows assumed to start on a line, as they do when nx * size is a
+// multiple of 128).  The staged kernel uses no offset.
+int x_shift(const mhd_params &p, int shape)
+{
+    const Shape &s = SHAPES[shape];
+    if (!s.pipe || !shape_fits(p, shape)) return 0;
+    const int es = p.precision, epl = 16 / es, L = 128 / es;
+    const int ntx = (p.nx + s.tx - 1) / s.tx;
+    int best = 0;
+    long bestc = -1;
+    // every box must stay within one period past nx: the kernel wraps indices once
+    for (int xs = 0; xs < L && ntx * s.tx + xs + 4 <= 2 * p.nx; xs += epl) {
+        long cnt = 0;
+        for (int t = 0; t < ntx; t++) {
+            int prev = -1;
+            for (int e = t * s.tx + xs - 4; e < t * s.tx + xs + s.tx + 4; e++) {
+                const int line = (((e % p.nx) + p.nx) % p.nx) / L;
+                if (line != prev) cnt++;
+                prev = line;
+            }
+        }
+        if (bestc < 0 || cnt < bestc) {
+            bestc = cnt;
+            best = xs;
+        }
+    }
+    return best;
 }
 
 int run_ntiles(const mhd_params &p, int shape)
@@ -488,6 +523,7 @@ mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *
     if (shape >= 0 && !shape_eligible(*p, shape, aligned)) shape = SHAPES[shape].pipe ? shape - 6 : shape;
     c->shape = shape >= 0 ? shape : default_shape(*p, aligned);
     c->fit = SHAPES[c->shape].pipe && shape_fits(*p, c->shape);
+    c->xs = x_shift(*p, c->shape);
     c->ntiles = run_ntiles(*p, c->shape);
     c->nb2 = run_nb2(*p, c->shape);
     mhd_status st = ctx_alloc_aux(c);
@@ -541,6 +577,7 @@ void fill_desc(const mhd_ctx *c, RunDesc<T> &d, int parity0, int64_t step0, cons
     d.first_tile = first_tile;
     d.ntiles = c->ntiles;
     d.fstride = c->fstride;
+    d.xs = c->xs;
     fill_coef<T>(c->p, d.c, d.dc);
     d.forcing = forcing;
     d.partials = partials;

@@ -25,6 +25,11 @@ constexpr int DIAGW = 10;  // per-tile partials: |B|^2, |u|^2, rho|u|^2, lnrho, 
 constexpr int DREC = 12;   // record: step, t, em, ek, urms, brms, umax, <lnrho>, <Bx>, <By>, <Bz>, nonfinite
 constexpr int FHEAD = 8;   // forcing block head: a[3], b[3], on, spare
 
+// Forcing phase tables hold (cos, sin) of one index in a 16-byte slot (FP32 pads
+// with two zeros), so that the ring kernel can copy them with 16-byte vectors.
+template <typename T>
+constexpr int FSLOT = 16 / (int)sizeof(T);
+
 // Sixth-order central weights (exact for polynomials of degree 6 / 7): first
 // derivative, offsets 1..3; second derivative, offsets 0..3.  The kernels take
 // them as compile-time constants (materialised by scalar moves, never loaded) and
@@ -72,10 +77,10 @@ template <typename T>
 struct RunDesc {
     T *buf[2][NF];
     int nx, ny, nz, parity0;
-    int first_tile, ntiles, fstride, pad;
+    int first_tile, ntiles, fstride, xs;  // xs: x offset of the tile grid (ring kernel only)
     Coef<T> c;
     DCoef dc;
-    const T *forcing;   // per batch step: FHEAD values then Ex[2nx], Ey[2ny], Ez[2nz]
+    const T *forcing;   // per batch step: FHEAD values then Ex, Ey, Ez (FSLOT values per index)
     double *partials;   // [ntiles][DIAGW]
     double *partials2;  // [nb2][DIAGW]: second level of the diagnostic reduction
     int nb2, pad2;      // blocks of the first finalize level (FIN_CHUNK partials each)
@@ -271,46 +276,6 @@ __device__ __forceinline__ void stage_store(T *dst, const T (&stage)[NL], int ti
     }
 }
 
-// The forcing term (held fixed over a step's substeps) at this thread's cells, in
-// two halves: load() issues the reads of the per-axis phase tables early, add()
-// folds f = a cos(theta) + b sin(theta) into the momentum accumulators later, once
-// the reads have long returned.
-template <typename T, int CZ>
-struct ForcingAt {
-    bool on = false;
-    T a[3], b[3];
-    T ex[CZ][2], ey[CZ][2], ez[CZ][2];
-
-    __device__ __forceinline__ void load(const RunDesc<T> &r, int step, const bool (&inside)[CZ],
-                                         const int (&gpos)[CZ][3])
-    {
-        const G<T> *fs = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
-        on = fs[6] != T(0);
-#pragma unroll
-        for (int q = 0; q < 3; q++) { a[q] = fs[q]; b[q] = fs[3 + q]; }
-        const G<T> *Ex = fs + FHEAD, *Ey = Ex + 2 * r.nx, *Ez = Ey + 2 * r.ny;
-#pragma unroll
-        for (int c = 0; c < CZ; c++) {
-            const int gx = inside[c] ? gpos[c][0] : 0, gy = inside[c] ? gpos[c][1] : 0, gz = inside[c] ? gpos[c][2] : 0;
-            ex[c][0] = Ex[2 * gx]; ex[c][1] = Ex[2 * gx + 1];
-            ey[c][0] = Ey[2 * gy]; ey[c][1] = Ey[2 * gy + 1];
-            ez[c][0] = Ez[2 * gz]; ez[c][1] = Ez[2 * gz + 1];
-        }
-    }
-
-    __device__ __forceinline__ void add(Cells<T, CZ> &C) const
-    {
-        if (!on) return;
-#pragma unroll
-        for (int c = 0; c < CZ; c++) {
-            const T pr = ex[c][0] * ey[c][0] - ex[c][1] * ey[c][1], pi = ex[c][0] * ey[c][1] + ex[c][1] * ey[c][0];
-            const T cr = pr * ez[c][0] - pi * ez[c][1], ci = pr * ez[c][1] + pi * ez[c][0];
-#pragma unroll
-            for (int q = 0; q < 3; q++) C.R[c][1 + q] += a[q] * cr + b[q] * ci;
-        }
-    }
-};
-
 // Forcing, RK3 update and diagnostic partials of this thread's cells (shared by
 // both substep kernels).  `red` is LDS scratch of at least 9 doubles per wave,
 // free once every thread has passed the preceding barrier.
@@ -324,14 +289,15 @@ __device__ __forceinline__ void finish(Cells<T, CZ> &C, const RunDesc<T> &r, con
         // forcing (held fixed over the step's substeps)
         const G<T> *fs = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
         if (FORCE && fs[6] != T(0)) {
-            const G<T> *Ex = fs + FHEAD, *Ey = Ex + 2 * r.nx, *Ez = Ey + 2 * r.ny;
+            constexpr int W = FSLOT<T>;
+            const G<T> *Ex = fs + FHEAD, *Ey = Ex + W * r.nx, *Ez = Ey + W * r.ny;
 #pragma unroll
             for (int c = 0; c < CZ; c++) {
                 if (!inside[c]) continue;
                 const int gx = gpos[c][0], gy = gpos[c][1], gz = gpos[c][2];
-                const T xr = Ex[2 * gx], xi = Ex[2 * gx + 1];
-                const T yr = Ey[2 * gy], yi = Ey[2 * gy + 1];
-                const T zr = Ez[2 * gz], zi = Ez[2 * gz + 1];
+                const T xr = Ex[W * gx], xi = Ex[W * gx + 1];
+                const T yr = Ey[W * gy], yi = Ey[W * gy + 1];
+                const T zr = Ez[W * gz], zi = Ez[W * gz + 1];
                 const T pr = xr * yr - xi * yi, pi = xr * yi + xi * yr;
                 const T cr = pr * zr - pi * zi, ci = pr * zi + pi * zr;
 #pragma unroll
@@ -584,6 +550,116 @@ __device__ __forceinline__ void ring_copy(const G<T> *src, T *buf, const uint32_
                                          (lds_void_t *)(buf + (v * NT + wave * 64) * EPL), 16, 0, 0);
 }
 
+// wait for this wave's LDS reads, then the work-group barrier
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unrestricted
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Direct-to-LDS copies issued per wave: every wave of a work-group issues the same
+// number, so that the vmcnt waits of the ring hold for each wave.
+template <typename T, int TX, int TY, int TZ, int NT, int NFI>
+struct Interior {
+    static constexpr int EPL = 16 / (int)sizeof(T);
+    static constexpr int NCELL = TX * TY * TZ, IV = NCELL / EPL;
+    static constexpr int NI = (NFI * IV + NT - 1) / NT;  // copies per wave
+    static_assert(IV % 64 == 0, "each wave's vectors lie in one field");
+
+    // the values of fields src[0..NFI) at the tile's cells; field k lands at
+    // area + k * NCELL, cells x fastest.  Cells past the grid edge read a clamped,
+    // valid address (their values are never used).
+    // (the sources are separate scalars, not an array: a dynamically indexed array of
+    // pointers would be placed in scratch memory)
+    static __device__ __forceinline__ void copy(const G<T> *s0, const G<T> *s1, const G<T> *s2, const G<T> *s3,
+                                                T *area, int wave, int lane, int x0s, int y0, int z0, int nx, int ny,
+                                                int nz)
+    {
+        static_assert(NFI >= 1 && NFI <= 4, "up to four fields");
+#pragma unroll
+        for (int i = 0; i < NI; i++) {
+            int qb = i * NT + wave * 64;                // first vector of this wave (uniform)
+            if (qb > NFI * IV - 64) qb = NFI * IV - 64;  // spare waves repeat the last vectors
+            const int f = qb / IV;
+            const G<T> *base = f == 0 ? s0 : (f == 1 ? s1 : (f == 2 ? s2 : s3));
+            const int c0 = (qb - f * IV + lane) * EPL;
+            const int x = c0 % TX, y = (c0 / TX) % TY, z = c0 / (TX * TY);
+            int gx = x0s + x;
+            gx -= gx >= nx ? nx : 0;
+            const int gy = min(y0 + y, ny - 1), gz = min(z0 + z, nz - 1);
+            const uint32_t off = (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz);
+            __builtin_amdgcn_global_load_lds((gconst_void_t *)(base + off), (lds_void_t *)(area + qb * EPL), 16, 0, 0);
+        }
+    }
+};
+
+// The step's forcing head and the phase-table slots of the tile's x, y and z indices
+// (one copy per wave, all waves writing the same values to the same place).
+template <typename T, int TX, int TY, int TZ>
+struct ForcingSlots {
+    static constexpr int EPL = 16 / (int)sizeof(T), HV = FHEAD / EPL;
+    static constexpr int NFV = HV + TX + TY + TZ;
+    static_assert(NFV <= 64, "one vector per lane");
+    static_assert(FSLOT<T> == EPL, "one table index per vector");
+
+    static __device__ __forceinline__ void copy(const G<T> *fs, T *area, int lane, int x0s, int y0, int z0, int nx,
+                                                int ny, int nz)
+    {
+        const G<T> *Ex = fs + FHEAD, *Ey = Ex + EPL * nx, *Ez = Ey + EPL * ny;
+        const G<T> *p = fs;
+        int j = lane;
+        if (j < HV) {
+            p = fs + j * EPL;
+        } else if ((j -= HV) < TX) {
+            int gx = x0s + j;
+            gx -= gx >= nx ? nx : 0;
+            p = Ex + EPL * gx;
+        } else if ((j -= TX) < TY) {
+            p = Ey + EPL * min(y0 + j, ny - 1);
+        } else if ((j -= TY) < TZ) {
+            p = Ez + EPL * min(z0 + j, nz - 1);
+        }
+        __builtin_amdgcn_global_load_lds((gconst_void_t *)p, (lds_void_t *)area, 16, 0, 0);
+    }
+
+    // f = a cos(theta) + b sin(theta) at this thread's cells, into the momentum sums
+    template <int CZ, int ZS>
+    static __device__ __forceinline__ void add(Cells<T, CZ> &C, const T *F, int lx, int ly, int lz0)
+    {
+        if (!(F[6] != T(0))) return;
+        const T *ex = F + (HV + lx) * EPL, *ey = F + (HV + TX + ly) * EPL;
+#pragma unroll
+        for (int c = 0; c < CZ; c++) {
+            const T *ez = F + (HV + TX + TY + lz0 + c * ZS) * EPL;
+            const T pr = ex[0] * ey[0] - ex[1] * ey[1], pi = ex[0] * ey[1] + ex[1] * ey[0];
+            const T cr = pr * ez[0] - pi * ez[1], ci = pr * ez[1] + pi * ez[0];
+#pragma unroll
+            for (int q = 0; q < 3; q++) C.R[c][1 + q] += F[q] * cr + F[3 + q] * ci;
+        }
+    }
+};
+
+// LDS bytes of the ring kernel (three ring buffers)
+template <typename T, int TX, int TY, int TZ, int CZ>
+constexpr int pipe_lds_bytes()
+{
+    constexpr int NT = TX * TY * (TZ / CZ), EPL = 16 / (int)sizeof(T);
+    constexpr int NVEC = (TX + 8) * (TY + 6) * (TZ + 6) / EPL;
+    return 3 * ((NVEC + NT - 1) / NT) * NT * 16;
+}
+
+// Every read of the pipeline is a direct-to-LDS copy, which the compiler's wait
+// analysis does not see; a register load issued before such copies would get a
+// full drain (vmcnt(0)) in front of its first use, stalling the prefetch.  So the
+// centre values, the forcing slots and the s-2 state also travel through LDS, in
+// ring buffers that are free at that moment, and every wait is explicit:
+//   start: forcing slots and centre values -> buffer 2, field 0 -> 0, field 4 -> 1
+//   pass 0: read centre and forcing from buffer 2, barrier, field 5 -> 2
+//   passes 1-4: the next field two ahead; pass 5: s-2 state of ln rho, u -> 1;
+//   pass 6: s-2 state of A -> 2; then the update reads them from LDS.
 template <typename T, int TX, int TY, int TZ, int CZ, int SUB, bool DIAG, bool STORE, int WPE, bool FIT>
 __global__ void __launch_bounds__(TX * TY * (TZ / CZ), WPE)
 k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
@@ -597,15 +673,26 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     constexpr int BUF = NV * NT * EPL;
     constexpr int SY = XW, SZ = XW * YW;
     constexpr int ZS = TZ / CZ;
+    constexpr int NCELL = TX * TY * TZ;
+    constexpr int FOFF = 64 * EPL;  // centre values follow the forcing slots in buffer 2
+    using Cen = Interior<T, TX, TY, TZ, NT, 4>;
+    using Old1 = Interior<T, TX, TY, TZ, NT, 4>;
+    using Old2 = Interior<T, TX, TY, TZ, NT, 3>;
+    using Frc = ForcingSlots<T, TX, TY, TZ>;
     static_assert(XW % EPL == 0 && TX % EPL == 0, "rows must hold whole vectors");
     static_assert(NT % 64 == 0, "whole waves");
+    static_assert(FOFF + 4 * NCELL <= BUF, "centre values and forcing slots fit one ring buffer");
+    static_assert(Cen::NI + 2 * NV < 64 && Old1::NI + Old2::NI < 64, "vmcnt is a 6-bit counter");
+    static_assert(!(DIAG && SUB != 0), "diagnostics are taken in substep 0 only");
 
     __shared__ __align__(16) T lds[3][BUF];
 
     const TileEnt te = tiles[blockIdx.x];
     const RunDesc<T> &r = runs[te.run];
     const int nx = r.nx, ny = r.ny, nz = r.nz;
-    const int x0 = te.xy & 0xffff, y0 = te.xy >> 16, z0 = te.z0;
+    // the tile grid is offset by xs cells in x (periodic), which places the rows of
+    // the halo box on fewer 128-byte lines; x0 is the unshifted origin
+    const int x0 = te.xy & 0xffff, y0 = te.xy >> 16, z0 = te.z0, x0s = x0 + r.xs;
     const int par = (r.parity0 + step) & 1;
     const int in_set = (SUB == 1) ? (par ^ 1) : par;
     const int out_set = (SUB == 1) ? par : (par ^ 1);
@@ -618,7 +705,7 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     }
 
     const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int lx = tid % TX, ly = (tid / TX) % TY, lz0 = tid / (TX * TY);
 
     // byte offsets of this thread's vectors of the halo box (same for every field)
@@ -629,7 +716,7 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         if (qv >= NVEC) qv = NVEC - 1;  // padding lanes re-read a valid vector
         const int q = qv * EPL;
         const int bx = q % XW, by = (q / XW) % YW, bz = q / SZ;
-        int gx = x0 - 4 + bx, gy = y0 - 3 + by, gz = z0 - 3 + bz;
+        int gx = x0s - 4 + bx, gy = y0 - 3 + by, gz = z0 - 3 + bz;
         if constexpr (FIT) {  // the box spans at most one period per axis
             gx += gx < 0 ? nx : (gx >= nx ? -nx : 0);
             gy += gy < 0 ? ny : (gy >= ny ? -ny : 0);
@@ -642,7 +729,7 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         voff[v] = (uint32_t)sizeof(T) * ((uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz));
     }
 
-    int cidx[CZ];
+    int cidx[CZ], icell[CZ];
     uint32_t gcell[CZ];
     bool inside[CZ];
     int gpos[CZ][3];
@@ -650,44 +737,43 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     for (int c = 0; c < CZ; c++) {
         const int lz = lz0 + c * ZS;
         cidx[c] = (lz + 3) * SZ + (ly + 3) * SY + (lx + 4);
-        gpos[c][0] = x0 + lx;
+        icell[c] = lx + TX * (ly + TY * lz);
+        gpos[c][0] = x0s + lx >= nx ? x0s + lx - nx : x0s + lx;
         gpos[c][1] = y0 + ly;
         gpos[c][2] = z0 + lz;
-        inside[c] = gpos[c][0] < nx && gpos[c][1] < ny && gpos[c][2] < nz;
+        inside[c] = x0 + lx < nx && gpos[c][1] < ny && gpos[c][2] < nz;
         gcell[c] = inside[c] ? (uint32_t)gpos[c][0] + (uint32_t)nx * ((uint32_t)gpos[c][1] + (uint32_t)ny * (uint32_t)gpos[c][2])
                              : 0u;
     }
 
+    KRegs<T> K;
+    K.load(r.c);
+    const DCoef &dc = r.dc;
+
+    // fields pass in the order ln rho, A_x, A_y, A_z, u_x, u_y, u_z; field k of that
+    // order lives in ring buffer k % 3 and is requested two passes ahead
+    if constexpr (STORE)
+        Frc::copy((const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride, lds[2], lane, x0s, y0, z0, nx, ny, nz);
+    Cen::copy(in[0], in[1], in[2], in[3], lds[2] + FOFF, wave, lane, x0s, y0, z0, nx, ny, nz);
+    ring_copy<T, NV, NT, EPL>(in[0], lds[0], voff, wave);
+    ring_copy<T, NV, NT, EPL>(in[4], lds[1], voff, wave);
+
     Cells<T, CZ> C;
+    ring_barrier<NV>();
 #pragma unroll
     for (int c = 0; c < CZ; c++) {
 #pragma unroll
         for (int f = 0; f < NF; f++) C.R[c][f] = T(0);
 #pragma unroll
         for (int a = 0; a < 3; a++) { C.B[c][a] = r.c.bext[a]; C.J[c][a] = T(0); C.Bd[c][a] = 0.0; }
-        C.v[c][0] = in[0][gcell[c]];
-        C.v[c][1] = in[1][gcell[c]];
-        C.v[c][2] = in[2][gcell[c]];
-        C.v[c][3] = in[3][gcell[c]];
+#pragma unroll
+        for (int f = 0; f < 4; f++) C.v[c][f] = lds[2][FOFF + f * NCELL + icell[c]];
     }
-    KRegs<T> K;
-    K.load(r.c);
-    const DCoef &dc = r.dc;
-    ForcingAt<T, CZ> frc;
-    if constexpr (STORE) frc.load(r, step, inside, gpos);
-    // the centre and forcing loads go out before any ring copy, so the waits for them
-    // do not also wait for the prefetched fields
-    __builtin_amdgcn_sched_barrier(0);
-
-    // fields pass in the order ln rho, A_x, A_y, A_z, u_x, u_y, u_z; field k of that
-    // order lives in ring buffer k % 3 and is requested two passes ahead
-    ring_copy<T, NV, NT, EPL>(in[0], lds[0], voff, wave);
-    ring_copy<T, NV, NT, EPL>(in[4], lds[1], voff, wave);
-
-    ring_barrier<NV>();
+    if constexpr (STORE) Frc::template add<CZ, ZS>(C, lds[2], lx, ly, lz0);
+    pin(C);
+    lds_barrier();  // buffer 2 is read out
     ring_copy<T, NV, NT, EPL>(in[5], lds[2], voff, wave);
     absorb<T, 0, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
-    if constexpr (STORE) frc.add(C);
 
     ring_barrier<NV>();
     ring_copy<T, NV, NT, EPL>(in[6], lds[0], voff, wave);
@@ -707,18 +793,29 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         absorb<T, 1, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
 
         ring_barrier<NV>();
+        if constexpr (SUB != 0)  // buffer 1 (u_x) is read out: the s-2 state of ln rho, u
+            Old1::copy(out[0], out[1], out[2], out[3], lds[1], wave, lane, x0s, y0, z0, nx, ny, nz);
         absorb<T, 2, SY, SZ, CZ, DIAG>(C, lds[2], cidx, K, dc);
 
-        ring_barrier<0>();
-        // the s-2 state at this thread's cells, needed by the update: request it now
         if constexpr (SUB != 0) {
-#pragma unroll
-            for (int c = 0; c < CZ; c++)
-#pragma unroll
-                for (int f = 0; f < NF; f++) C.old[c][f] = inside[c] ? out[f][gcell[c]] : T(0);
-            C.have_old = true;
+            ring_barrier<Old1::NI>();
+            // buffer 2 (u_y) is read out: the s-2 state of A
+            Old2::copy(out[4], out[5], out[6], out[6], lds[2], wave, lane, x0s, y0, z0, nx, ny, nz);
+        } else {
+            ring_barrier<0>();
         }
         absorb<T, 3, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+        if constexpr (SUB != 0) {
+            ring_barrier<0>();
+#pragma unroll
+            for (int c = 0; c < CZ; c++) {
+#pragma unroll
+                for (int f = 0; f < 4; f++) C.old[c][f] = lds[1][f * NCELL + icell[c]];
+#pragma unroll
+                for (int f = 4; f < NF; f++) C.old[c][f] = lds[2][(f - 4) * NCELL + icell[c]];
+            }
+            C.have_old = true;
+        }
     } else {
         ring_barrier<NV>();
         absorb<T, 5, SY, SZ, CZ, DIAG>(C, lds[2], cidx, K, dc);

@@ -35,6 +35,7 @@ struct mhd_ctx {
     hipStream_t stream = nullptr;
     int shape = 0;
     bool fit = false;        // halo box spans at most one period per axis (cheap wrap)
+    int xs = 0;              // x offset of the tile grid (ring kernel)
     int ntiles = 0;
     int fstride = 0;
     bool owns = false;
@@ -95,5 +96,6 @@ hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs,
 template <typename T>
 hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int max_nb2, int step, hipStream_t st);
 int run_nb2(const mhd_params &p, int shape);
+int x_shift(const mhd_params &p, int shape);
 
 }  // namespace mhd
