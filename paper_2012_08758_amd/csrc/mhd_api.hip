@@ -59,7 +59,28 @@ const Shape SHAPES[NSHAPES] = {
     {16, 8, 8, 2, true},    // 9
     {32, 4, 4, 1, true},    // 10
     {16, 16, 4, 2, true},   // 11
+    // z-marching column kernel (ring per field in LDS): the tile divides the grid
+    {16, 8, 4, 1, true, true},  // 12: FP32 only (the FP64 rings do not fit the LDS)
+    {8, 8, 4, 1, true, true},   // 13
 };
+
+// the shape used when `shape` cannot run on a grid: march -> ring -> staged, same box
+int shape_fallback(int shape)
+{
+    if (shape == 12) return 6;
+    if (shape == 13) return 8;
+    return SHAPES[shape].pipe ? shape - 6 : shape;
+}
+
+static bool march_lds_fits(int shape, int precision)
+{
+    const Shape &s = SHAPES[shape];
+    if (s.tx == 16 && s.ty == 8 && s.tz == 4)
+        return precision == MHD_FP64 ? MarchCfg<double, 16, 8, 4>::FITS : MarchCfg<float, 16, 8, 4>::FITS;
+    if (s.tx == 8 && s.ty == 8 && s.tz == 4)
+        return precision == MHD_FP64 ? MarchCfg<double, 8, 8, 4>::FITS : MarchCfg<float, 8, 8, 4>::FITS;
+    return false;
+}
 
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int>, int> g_tuned;  // (nx, ny, nz, prec) -> shape
@@ -67,9 +88,13 @@ static std::map<std::tuple<int, int, int, int>, int> g_tuned;  // (nx, ny, nz, p
 bool shape_eligible(const mhd_params &p, int shape, bool aligned)
 {
     if (shape < 0 || shape >= NSHAPES) return false;
-    if (!SHAPES[shape].pipe) return true;
+    const Shape &s = SHAPES[shape];
+    if (!s.pipe) return true;
     const int epl = 16 / p.precision;
-    return aligned && p.nx % epl == 0;
+    if (!(aligned && p.nx % epl == 0)) return false;
+    if (!s.march) return true;
+    return march_lds_fits(shape, p.precision) && p.nx % s.tx == 0 && p.ny % s.ty == 0 && p.nz % s.tz == 0 &&
+           p.nx >= s.tx + 8 && p.ny >= s.ty + 6;
 }
 
 bool shape_fits(const mhd_params &p, int shape)
@@ -92,7 +117,7 @@ int default_shape(const mhd_params &p, bool aligned)
         const double n = (double)p.nx * p.ny * p.nz;
         want = n <= 64.0 * 64 * 64 ? 8 : (p.precision == MHD_FP64 ? 9 : 10);
     }
-    if (!shape_eligible(p, want, aligned)) want = SHAPES[want].pipe ? want - 6 : want;
+    while (!shape_eligible(p, want, aligned)) want = shape_fallback(want);
     return want;
 }
 
@@ -288,9 +313,42 @@ mhd_status check_params(const mhd_params *p)
 // L2 when the next level reads it.  (In plain z-y-x order the z neighbours of a tile
 // are thousands of tiles away and every z halo is fetched from HBM again.)
 // tir (the partials slot) stays the natural z-y-x index.
+// z-segments of a marching run: enough work-groups to fill the chip (one resident per
+// CU), each segment a whole number of slabs of at least two slabs
+int march_segment(const mhd_params &p, int shape)
+{
+    const Shape &s = SHAPES[shape];
+    if (!s.march) return 0;
+    const long ncol = (long)(p.nx / s.tx) * (p.ny / s.ty);
+    int nseg = 1;
+    while (ncol * nseg < 1024 && p.nz % (2 * nseg * s.tz) == 0 && p.nz / (2 * nseg) >= 2 * s.tz) nseg *= 2;
+    return p.nz / nseg;
+}
+
 void run_tiles(const mhd_params &p, int shape, int run, std::vector<TileEnt> &out)
 {
     const Shape &s = SHAPES[shape];
+    if (s.march) {
+        // columns in patches of ~32 (the work-groups resident on one XCD at a time), so
+        // that columns marching side by side share their x/y halo lines in L2
+        const int ntx = p.nx / s.tx, nty = p.ny / s.ty, seg = march_segment(p, shape), nseg = p.nz / seg;
+        int px = 1;
+        while (px * 2 <= ntx && px * px * 2 <= 32) px *= 2;
+        const int py = std::max(1, std::min(nty, 32 / px));
+        for (int pY = 0; pY < nty; pY += py)
+            for (int pX = 0; pX < ntx; pX += px)
+                for (int sg = 0; sg < nseg; sg++)
+                    for (int ty = pY; ty < std::min(nty, pY + py); ty++)
+                        for (int tx = pX; tx < std::min(ntx, pX + px); tx++) {
+                            TileEnt t;
+                            t.run = run;
+                            t.xy = (tx * s.tx) | ((ty * s.ty) << 16);
+                            t.z0 = sg * seg;
+                            t.tir = tx + ntx * (ty + nty * sg);
+                            out.push_back(t);
+                        }
+        return;
+    }
     const int ntx = (p.nx + s.tx - 1) / s.tx, nty = (p.ny + s.ty - 1) / s.ty, ntz = (p.nz + s.tz - 1) / s.tz;
     // columns per patch ~ resident work-groups per XCD (32 CUs x 1-2 groups)
     const int target = p.precision == MHD_FP64 ? 32 : 64;
@@ -347,6 +405,7 @@ int x_shift(const mhd_params &p, int shape)
 int run_ntiles(const mhd_params &p, int shape)
 {
     const Shape &s = SHAPES[shape];
+    if (s.march) return (p.nx / s.tx) * (p.ny / s.ty) * (p.nz / march_segment(p, shape));
     return ((p.nx + s.tx - 1) / s.tx) * ((p.ny + s.ty - 1) / s.ty) * ((p.nz + s.tz - 1) / s.tz);
 }
 
@@ -408,6 +467,26 @@ static hipError_t launch_pipe_fit(bool fit, int kind, const RunDesc<T> *runs, co
                : launch_pipe<T, TX, TY, TZ, CZ, false>(kind, runs, tiles, ntiles, step, st);
 }
 
+template <typename T, int TX, int TY, int TZ>
+static hipError_t launch_march(int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles, int step,
+                               hipStream_t st)
+{
+    if constexpr (!MarchCfg<T, TX, TY, TZ>::FITS) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int NT = TX * TY * TZ;
+        constexpr int W = NT >= 512 ? 2 : 1;  // one work-group per CU (LDS)
+        const dim3 grid(ntiles), block(NT);
+        switch (kind) {
+        case 0: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 0, true, true, W>), grid, block, 0, st, runs, tiles, step); break;
+        case 1: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 1, false, true, W>), grid, block, 0, st, runs, tiles, step); break;
+        case 2: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 2, false, true, W>), grid, block, 0, st, runs, tiles, step); break;
+        default: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 0, true, false, W>), grid, block, 0, st, runs, tiles, step); break;
+        }
+        return hipGetLastError();
+    }
+}
+
 template <typename T>
 hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles,
                           int step, hipStream_t st)
@@ -425,7 +504,9 @@ hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs,
     case 8: return launch_pipe_fit<T, 8, 8, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
     case 9: return launch_pipe_fit<T, 16, 8, 8, 2>(fit, kind, runs, tiles, ntiles, step, st);
     case 10: return launch_pipe_fit<T, 32, 4, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
-    default: return launch_pipe_fit<T, 16, 16, 4, 2>(fit, kind, runs, tiles, ntiles, step, st);
+    case 11: return launch_pipe_fit<T, 16, 16, 4, 2>(fit, kind, runs, tiles, ntiles, step, st);
+    case 12: return launch_march<T, 16, 8, 4>(kind, runs, tiles, ntiles, step, st);
+    default: return launch_march<T, 8, 8, 4>(kind, runs, tiles, ntiles, step, st);
     }
 }
 
@@ -520,10 +601,12 @@ mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *
     }
     // tile shape: the requested one if this grid and these buffers can use it, else the
     // (tuned or default) choice; ring shapes fall back to the staged kernel of the same box
-    if (shape >= 0 && !shape_eligible(*p, shape, aligned)) shape = SHAPES[shape].pipe ? shape - 6 : shape;
+    if (shape >= 0)
+        while (!shape_eligible(*p, shape, aligned)) shape = shape_fallback(shape);
     c->shape = shape >= 0 ? shape : default_shape(*p, aligned);
     c->fit = SHAPES[c->shape].pipe && shape_fits(*p, c->shape);
     c->xs = x_shift(*p, c->shape);
+    c->seg = march_segment(*p, c->shape);
     c->ntiles = run_ntiles(*p, c->shape);
     c->nb2 = run_nb2(*p, c->shape);
     mhd_status st = ctx_alloc_aux(c);
@@ -578,6 +661,7 @@ void fill_desc(const mhd_ctx *c, RunDesc<T> &d, int parity0, int64_t step0, cons
     d.ntiles = c->ntiles;
     d.fstride = c->fstride;
     d.xs = c->xs;
+    d.seg = c->seg;
     fill_coef<T>(c->p, d.c, d.dc);
     d.forcing = forcing;
     d.partials = partials;
@@ -1024,7 +1108,7 @@ mhd_status mhd_tile_config(const mhd_params *p, char *buf, size_t len)
     if (st != MHD_OK) return st;
     if (!buf || len == 0) return fail(MHD_E_INVALID, "buffer is NULL");
     const Shape &s = SHAPES[default_shape(*p)];
-    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.pipe ? "+ring" : "");
+    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.march ? "+march" : (s.pipe ? "+ring" : ""));
     return MHD_OK;
 }
 
@@ -1042,7 +1126,7 @@ mhd_status mhd_tile_shape_name(int32_t i, char *buf, size_t len)
 {
     if (i < 0 || i >= NSHAPES || !buf || len == 0) return fail(MHD_E_INVALID, "bad tile shape index or buffer");
     const Shape &s = SHAPES[i];
-    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.pipe ? "+ring" : "");
+    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.march ? "+march" : (s.pipe ? "+ring" : ""));
     return MHD_OK;
 }
 

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mhd {
 
 // Pointers that the kernels dereference are cast to the global address space, so
@@ -48,7 +50,7 @@ struct Coef {
     T brho[3];    // beta_s * alpha_s / beta_{s-1} (0 for s = 0)
 };
 
-struct DCoef {      // FP64 inverse spacings and mean field, for diagnostics of FP32 runs
+struct DCoef {      // FP64 inverse spacings and mean field, for the diagnostics
     double ih1[3];
     double bext[3];
 };
@@ -83,7 +85,8 @@ struct RunDesc {
     const T *forcing;   // per batch step: FHEAD values then Ex, Ey, Ez (FSLOT values per index)
     double *partials;   // [ntiles][DIAGW]
     double *partials2;  // [nb2][DIAGW]: second level of the diagnostic reduction
-    int nb2, pad2;      // blocks of the first finalize level (FIN_CHUNK partials each)
+    int nb2;            // blocks of the first finalize level (FIN_CHUNK partials each)
+    int seg;            // z-marching kernel: planes per z-segment of a column
     double *records;    // [batch step][DREC]
     double step0;       // global step index of batch step 0
     double t0, dt;
@@ -119,12 +122,12 @@ __device__ __forceinline__ T sdm(const T *s, int sa, int sb, T ihm)
                   T(W2_3) * ((s[3 * p] + s[-3 * p]) - (s[3 * q] + s[-3 * q])));
 }
 
+// first derivative of FP32 values evaluated in FP64
 __device__ __forceinline__ double sd1d(const float *s, int st, double ih)
 {
     return ih * (W1_1 * ((double)s[st] - (double)s[-st]) + W1_2 * ((double)s[2 * st] - (double)s[-2 * st]) +
                  W1_3 * ((double)s[3 * st] - (double)s[-3 * st]));
 }
-__device__ __forceinline__ double sd1d(const double *s, int st, double ih) { return sd1(s, st, ih); }
 
 __device__ __forceinline__ bool finite_v(float v) { return __builtin_isfinite(v); }
 __device__ __forceinline__ bool finite_v(double v) { return __builtin_isfinite(v); }
@@ -179,7 +182,6 @@ template <typename T, int F, int SY, int SZ, int CZ, bool DIAG>
 __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&cidx)[CZ], const KRegs<T> &K,
                                        const DCoef &dc)
 {
-    constexpr bool IS_F64 = sizeof(T) == 8;
     constexpr int s0 = 1, s1 = SY, s2 = SZ;
 #pragma unroll
     for (int c = 0; c < CZ; c++) {
@@ -211,8 +213,8 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
             const T e2 = sd1(s, st2, K.ih1[b2]);
             C.B[c][b1] += e2;
             C.B[c][b2] -= e1;
-            if constexpr (DIAG) {
-                if constexpr (IS_F64) {
+            if constexpr (DIAG) {  // FP64 curl for the diagnostics (recomputed for FP32 states)
+                if constexpr (sizeof(T) == 8) {
                     C.Bd[c][b1] += (double)e2;
                     C.Bd[c][b2] -= (double)e1;
                 } else {
@@ -274,6 +276,32 @@ __device__ __forceinline__ void stage_store(T *dst, const T (&stage)[NL], int ti
         const int q = tid + k * NT;
         if (k < NL - 1 || q < VOL) dst[q] = stage[k];
     }
+}
+
+// One DPP move of a double (two 32-bit halves); lanes without a source read 0, the
+// identity of both reductions below (the maxima are of non-negative values).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum (or maximum) over the 64 lanes of a wave, valid in lane 63: shifts right by 1,
+// 2, 4, 8 within each row of 16 lanes, then row 0/2 totals broadcast into rows 1/3
+// (row_bcast:15), then the row 1 total into rows 2 and 3 (row_bcast:31).
+template <bool MAX>
+__device__ __forceinline__ double wave_reduce(double v)
+{
+    auto op = [](double a, double b) { return MAX ? fmax(a, b) : a + b; };
+    v = op(v, dpp_move<0x111, 0xF>(v));
+    v = op(v, dpp_move<0x112, 0xF>(v));
+    v = op(v, dpp_move<0x114, 0xF>(v));
+    v = op(v, dpp_move<0x118, 0xF>(v));
+    v = op(v, dpp_move<0x142, 0xA>(v));
+    v = op(v, dpp_move<0x143, 0xC>(v));
+    return v;
 }
 
 // Forcing, RK3 update and diagnostic partials of this thread's cells (shared by
@@ -347,19 +375,14 @@ __device__ __forceinline__ void finish(Cells<T, CZ> &C, const RunDesc<T> &r, con
             for (int f = 0; f < NF; f++) ok = ok && finite_v(C.v[c][f]);
             acc[8] += ok ? 0.0 : 1.0;
         }
-        // wave reduction, then across waves through LDS (fixed order: deterministic)
+        // wave reduction with DPP row moves (VALU only, no LDS traffic), totals in lane
+        // 63; then across waves through LDS (fixed order: deterministic)
 #pragma unroll
-        for (int q = 0; q < 9; q++) {
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const double w = __shfl_xor(acc[q], o, 64);
-                acc[q] = (q == 7) ? fmax(acc[q], w) : acc[q] + w;
-            }
-        }
+        for (int q = 0; q < 9; q++) acc[q] = (q == 7) ? wave_reduce<true>(acc[q]) : wave_reduce<false>(acc[q]);
         constexpr int NW = NT / 64;
         __syncthreads();
         const int wave = tid / 64, lane = tid % 64;
-        if (lane == 0) {
+        if (lane == 63) {
 #pragma unroll
             for (int q = 0; q < 9; q++) red[wave * 9 + q] = acc[q];
         }
@@ -826,6 +849,437 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     __builtin_amdgcn_sched_barrier(0);
     finish<T, CZ, NT, SUB, DIAG, STORE, false>(C, r, te, r.c, dc, inside, gcell, gpos, out,
                                                  reinterpret_cast<double *>(&lds[1][0]), step, tid);
+}
+
+// ------------------------------------------------------------------ z-marching variant
+//
+// A work-group owns one TX x TY column of one run and marches through a z-segment in
+// slabs of TZ planes (one cell per thread).  Every field keeps a ring of TZ + 6
+// planes in LDS, the planes z-3 .. z+TZ+2 of the current slab.  Once a field's pass
+// of a slab is done its TZ oldest planes are dead, and the next slab's TZ planes are
+// requested into their slots, six passes ahead of use.  Planes shared by consecutive
+// slabs therefore come from memory once; only the x and y halos are re-read, by the
+// neighbouring columns (which march at the same time, so they meet in L2).  The
+// z-stencil reaches into the ring through seven per-thread plane pointers.
+//
+// Terms that need a field at the cell before its pass has come (the advection of
+// ln rho and u, the induction u x B) are kept as their factors and added at the end
+// of the slab, so that the pipeline needs no out-of-order waits.
+
+template <typename T, int SY>
+struct PlaneAcc {
+    const T *zp[7];  // this cell's (x, y) in the planes z-3 .. z+3
+    template <int DX, int DY, int DZ>
+    __device__ __forceinline__ T get() const
+    {
+        return zp[DZ + 3][DX + DY * SY];
+    }
+};
+
+template <int AX, int M>
+struct Ax {
+    static constexpr int x = AX == 0 ? M : 0, y = AX == 1 ? M : 0, z = AX == 2 ? M : 0;
+};
+
+template <typename T, int AX, class A>
+__device__ __forceinline__ T gd1(const A &a, T ih)
+{
+    using P1 = Ax<AX, 1>;
+    using P2 = Ax<AX, 2>;
+    using P3 = Ax<AX, 3>;
+    return ih * (T(W1_1) * (a.template get<P1::x, P1::y, P1::z>() - a.template get<-P1::x, -P1::y, -P1::z>()) +
+                 T(W1_2) * (a.template get<P2::x, P2::y, P2::z>() - a.template get<-P2::x, -P2::y, -P2::z>()) +
+                 T(W1_3) * (a.template get<P3::x, P3::y, P3::z>() - a.template get<-P3::x, -P3::y, -P3::z>()));
+}
+
+template <typename T, int AX, class A>
+__device__ __forceinline__ T gd2(const A &a, T ih2)
+{
+    using P1 = Ax<AX, 1>;
+    using P2 = Ax<AX, 2>;
+    using P3 = Ax<AX, 3>;
+    return ih2 * (T(W2_0) * a.template get<0, 0, 0>() +
+                  T(W2_1) * (a.template get<P1::x, P1::y, P1::z>() + a.template get<-P1::x, -P1::y, -P1::z>()) +
+                  T(W2_2) * (a.template get<P2::x, P2::y, P2::z>() + a.template get<-P2::x, -P2::y, -P2::z>()) +
+                  T(W2_3) * (a.template get<P3::x, P3::y, P3::z>() + a.template get<-P3::x, -P3::y, -P3::z>()));
+}
+
+template <int AX, class A>
+__device__ __forceinline__ double gd1d(const A &a, double ih)
+{
+    using P1 = Ax<AX, 1>;
+    using P2 = Ax<AX, 2>;
+    using P3 = Ax<AX, 3>;
+    auto d = [&](auto v) { return (double)v; };
+    return ih * (W1_1 * (d(a.template get<P1::x, P1::y, P1::z>()) - d(a.template get<-P1::x, -P1::y, -P1::z>())) +
+                 W1_2 * (d(a.template get<P2::x, P2::y, P2::z>()) - d(a.template get<-P2::x, -P2::y, -P2::z>())) +
+                 W1_3 * (d(a.template get<P3::x, P3::y, P3::z>()) - d(a.template get<-P3::x, -P3::y, -P3::z>())));
+}
+
+// d_a d_b from the (a+b) and (a-b) diagonals
+template <typename T, int AA, int AB, class A>
+__device__ __forceinline__ T gdm(const A &a, T ihm)
+{
+    constexpr int px = Ax<AA, 1>::x + Ax<AB, 1>::x, py = Ax<AA, 1>::y + Ax<AB, 1>::y, pz = Ax<AA, 1>::z + Ax<AB, 1>::z;
+    constexpr int qx = Ax<AA, 1>::x - Ax<AB, 1>::x, qy = Ax<AA, 1>::y - Ax<AB, 1>::y, qz = Ax<AA, 1>::z - Ax<AB, 1>::z;
+    return ihm * (T(W2_1) * ((a.template get<px, py, pz>() + a.template get<-px, -py, -pz>()) -
+                             (a.template get<qx, qy, qz>() + a.template get<-qx, -qy, -qz>())) +
+                  T(W2_2) * ((a.template get<2 * px, 2 * py, 2 * pz>() + a.template get<-2 * px, -2 * py, -2 * pz>()) -
+                             (a.template get<2 * qx, 2 * qy, 2 * qz>() + a.template get<-2 * qx, -2 * qy, -2 * qz>())) +
+                  T(W2_3) * ((a.template get<3 * px, 3 * py, 3 * pz>() + a.template get<-3 * px, -3 * py, -3 * pz>()) -
+                             (a.template get<3 * qx, 3 * qy, 3 * qz>() + a.template get<-3 * qx, -3 * qy, -3 * qz>())));
+}
+
+// per-cell accumulators of the marching kernel
+template <typename T>
+struct CellM {
+    T v[NF];      // centre values
+    T g[3];       // grad ln rho
+    T B[3], J[3];
+    T R[NF];
+    T du[3][3];   // du[m][a] = d_a u_m, for the advection added at the end
+    double Bd[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void pin(CellM<T> &C)
+{
+#pragma unroll
+    for (int f = 0; f < NF; f++) asm volatile("" : "+v"(C.R[f]), "+v"(C.v[f]));
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        asm volatile("" : "+v"(C.g[a]), "+v"(C.B[a]), "+v"(C.J[a]), "+v"(C.Bd[a]));
+        asm volatile("" : "+v"(C.du[a][0]), "+v"(C.du[a][1]), "+v"(C.du[a][2]));
+    }
+}
+
+// Fold field F's derivatives at this cell into the accumulators (same terms as
+// absorb, with the advection and induction deferred).
+template <typename T, int F, bool DIAG, class A>
+__device__ __forceinline__ void absorb_m(CellM<T> &C, const A &s, const KRegs<T> &K, const DCoef &dc)
+{
+    if constexpr (F == 0) {
+        C.v[0] = s.template get<0, 0, 0>();
+        C.g[0] = gd1<T, 0>(s, K.ih1[0]);
+        C.g[1] = gd1<T, 1>(s, K.ih1[1]);
+        C.g[2] = gd1<T, 2>(s, K.ih1[2]);
+        C.R[1] -= K.cs2 * C.g[0];
+        C.R[2] -= K.cs2 * C.g[1];
+        C.R[3] -= K.cs2 * C.g[2];
+    } else if constexpr (F >= 4) {
+        constexpr int m = F - 4;
+        constexpr int b1 = (m + 1) % 3, b2 = (m + 2) % 3;
+        C.v[F] = s.template get<0, 0, 0>();
+        const T d2m = gd2<T, m>(s, K.ih2[m]);
+        const T d21 = gd2<T, b1>(s, K.ih2[b1]);
+        const T d22 = gd2<T, b2>(s, K.ih2[b2]);
+        C.R[F] += K.eta * (d2m + d21 + d22);
+        C.J[m] -= d21 + d22;
+        C.J[b1] += gdm<T, b1, m>(s, K.ihm[Pair<b1, m>::v]);
+        C.J[b2] += gdm<T, b2, m>(s, K.ihm[Pair<b2, m>::v]);
+        const T e1 = gd1<T, b1>(s, K.ih1[b1]);
+        const T e2 = gd1<T, b2>(s, K.ih1[b2]);
+        C.B[b1] += e2;
+        C.B[b2] -= e1;
+        if constexpr (DIAG) {  // FP64 curl for the diagnostics (recomputed for FP32 states)
+            if constexpr (sizeof(T) == 8) {
+                C.Bd[b1] += (double)e2;
+                C.Bd[b2] -= (double)e1;
+            } else {
+                C.Bd[b1] += gd1d<b2>(s, dc.ih1[b2]);
+                C.Bd[b2] -= gd1d<b1>(s, dc.ih1[b1]);
+            }
+        }
+        if constexpr (F == 6) {  // A complete: Lorentz force (ln rho is known)
+            const T rinv = exp(-C.v[0]);
+            const T *Bv = C.B, *Jv = C.J;
+            C.R[1] += rinv * (Jv[1] * Bv[2] - Jv[2] * Bv[1]);
+            C.R[2] += rinv * (Jv[2] * Bv[0] - Jv[0] * Bv[2]);
+            C.R[3] += rinv * (Jv[0] * Bv[1] - Jv[1] * Bv[0]);
+        }
+    } else {
+        constexpr int m = F - 1;
+        constexpr int b1 = (m + 1) % 3, b2 = (m + 2) % 3;
+        C.v[F] = s.template get<0, 0, 0>();
+        T du[3];
+        du[m] = gd1<T, m>(s, K.ih1[m]);
+        du[b1] = gd1<T, b1>(s, K.ih1[b1]);
+        du[b2] = gd1<T, b2>(s, K.ih1[b2]);
+        const T d2m = gd2<T, m>(s, K.ih2[m]);
+        const T lap = d2m + gd2<T, b1>(s, K.ih2[b1]) + gd2<T, b2>(s, K.ih2[b2]);
+        const T *g = C.g;
+        T rm = K.nu * lap + K.nu3 * d2m;
+        rm += K.nu * (du[0] * g[0] + du[1] * g[1] + du[2] * g[2]);
+        C.R[1 + m] += rm;
+        C.R[0] -= du[m];
+#pragma unroll
+        for (int a = 0; a < 3; a++) C.R[1 + a] += K.nu * du[a] * g[m] - K.nu2_3 * du[m] * g[a];
+        C.R[1 + b1] += K.nu3 * gdm<T, b1, m>(s, K.ihm[Pair<b1, m>::v]);
+        C.R[1 + b2] += K.nu3 * gdm<T, b2, m>(s, K.ihm[Pair<b2, m>::v]);
+#pragma unroll
+        for (int a = 0; a < 3; a++) C.du[m][a] = du[a];
+    }
+    pin(C);
+}
+
+// Planes [za, za + n) of one field into its ring (slot of plane z: (z - zbase) mod P),
+// one 16-byte vector per lane, every wave issuing the same number of copies.  A plane
+// slot holds SLOTV vectors (whole waves); lanes past the plane's PV vectors and waves
+// past the last plane repeat valid reads into their own (padding or repeated) slot.
+template <typename T, int TX, int TY, int NT, int P, int SLOTV, int NPL>
+__device__ __forceinline__ void plane_copy(const G<T> *src, T *ring, int za, int zbase, int wave, int lane, int x0s,
+                                           int y0, int nx, int ny, int nz)
+{
+    constexpr int EPL = 16 / (int)sizeof(T);
+    constexpr int XW = TX + 8, YW = TY + 6, PV = XW * YW / EPL;
+    constexpr int NI = (NPL * SLOTV + NT - 1) / NT;
+#pragma unroll
+    for (int i = 0; i < NI; i++) {
+        const int qb = i * NT + wave * 64;  // wave-uniform
+        int k = qb / SLOTV;
+        const int vb = qb - k * SLOTV;
+        if (k >= NPL) k = NPL - 1;
+        const int z = za + k;
+        int slot = (z - zbase) % P;
+        slot += slot < 0 ? P : 0;
+        int gz = z % nz;
+        gz += gz < 0 ? nz : 0;
+        int v = vb + lane;
+        if (v >= PV) v = 0;
+        const int e = v * EPL, row = e / XW, col = e - row * XW;
+        int gx = x0s - 4 + col, gy = y0 - 3 + row;
+        gx += gx < 0 ? nx : (gx >= nx ? -nx : 0);
+        gy += gy < 0 ? ny : (gy >= ny ? -ny : 0);
+        const uint32_t off = (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz);
+        __builtin_amdgcn_global_load_lds((gconst_void_t *)(src + off),
+                                         (lds_void_t *)(ring + slot * SLOTV * EPL + vb * EPL), 16, 0, 0);
+    }
+}
+
+// LDS layout and copy counts of the marching kernel
+template <typename T, int TX, int TY, int TZ>
+struct MarchCfg {
+    static constexpr int NT = TX * TY * TZ, EPL = 16 / (int)sizeof(T);
+    static constexpr int XW = TX + 8, YW = TY + 6, SY = XW;
+    static constexpr int PV = XW * YW / EPL;
+    static constexpr int SLOTV = (PV + 63) / 64 * 64;  // plane slot, whole waves of vectors
+    static constexpr int SLOT = SLOTV * EPL;           // elements
+    static constexpr int P = TZ + 6;                   // planes per field ring
+    static constexpr int RING = P * SLOT;
+    static constexpr int ND = (TZ * SLOTV + NT - 1) / NT;  // copies per wave, one field, one slab
+    static constexpr int IV = NT / EPL;
+    static constexpr int LDS_ELEMS = NF * RING + NF * NT + 64 * EPL;
+    static constexpr int LDS_BYTES = LDS_ELEMS * (int)sizeof(T);
+    static constexpr bool FITS = LDS_BYTES <= 160 * 1024;
+};
+
+template <typename T, int TX, int TY, int TZ, int SUB, bool DIAG, bool STORE, int WPE>
+__global__ void __launch_bounds__(TX * TY * TZ, WPE)
+k_march(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
+{
+    using M = MarchCfg<T, TX, TY, TZ>;
+    constexpr int NT = M::NT, EPL = M::EPL, SY = M::SY, P = M::P, SLOT = M::SLOT, RING = M::RING;
+    constexpr int ND = M::ND;
+    using Old = Interior<T, TX, TY, TZ, NT, 4>;
+    using Old3 = Interior<T, TX, TY, TZ, NT, 3>;
+    using Frc = ForcingSlots<T, TX, TY, TZ>;
+    constexpr bool OLDS = STORE && SUB != 0;
+    constexpr int NO = OLDS ? Old::NI + Old3::NI : 0;  // s-2 state copies per slab
+    constexpr int NFC = STORE ? 1 : 0;                 // forcing-slot copy per slab
+    constexpr int ES = STORE ? NF : 0;                 // stores per slab
+    static_assert(M::FITS, "rings, s-2 state and forcing slots fit the LDS");
+    static_assert(M::XW % EPL == 0 && TX % EPL == 0, "rows must hold whole vectors");
+    static_assert(5 * ND + ES + NO + NFC < 64, "vmcnt is a 6-bit counter");
+    static_assert(!(DIAG && SUB != 0), "diagnostics are taken in substep 0 only");
+
+    __shared__ __align__(16) T lds[M::LDS_ELEMS];
+    T *const old_area = lds + NF * RING;
+    T *const frc = old_area + NF * NT;
+
+    const TileEnt te = tiles[blockIdx.x];
+    const RunDesc<T> &r = runs[te.run];
+    const int nx = r.nx, ny = r.ny, nz = r.nz;
+    const int x0 = te.xy & 0xffff, y0 = te.xy >> 16, zs0 = te.z0, x0s = x0 + r.xs;
+    const int nslab = r.seg / TZ;
+    const int zbase = zs0 - 3;
+    const int par = (r.parity0 + step) & 1;
+    const int in_set = (SUB == 1) ? (par ^ 1) : par;
+    const int out_set = (SUB == 1) ? par : (par ^ 1);
+    const G<T> *in[NF];
+    G<T> *out[NF];
+#pragma unroll
+    for (int f = 0; f < NF; f++) {
+        in[f] = (const G<T> *)r.buf[in_set][f];
+        out[f] = (G<T> *)r.buf[out_set][f];
+    }
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int gxc = x0s + lx >= nx ? x0s + lx - nx : x0s + lx, gyc = y0 + ly;
+    const int xyoff = (ly + 3) * SY + (lx + 4);
+
+    KRegs<T> K;
+    K.load(r.c);
+    const DCoef &dc = r.dc;
+    const G<T> *fblk = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
+
+    // field at each position of the pass order (ln rho, A, u) and its ring
+    constexpr int SEQ[NF] = {0, 4, 5, 6, 1, 2, 3};
+    auto ring = [&](int pos) { return lds + pos * RING; };
+    auto planes = [&](int pos, int za, auto nplc) {
+        constexpr int NPL = decltype(nplc)::value;
+        plane_copy<T, TX, TY, NT, P, M::SLOTV, NPL>(in[SEQ[pos]], ring(pos), za, zbase, wave, lane, x0s, y0, nx, ny,
+                                                   nz);
+    };
+    using TZc = std::integral_constant<int, TZ>;
+    using Pc = std::integral_constant<int, P>;
+
+    double acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) acc[q] = 0.0;
+
+    // prologue: every field's first window
+#pragma unroll
+    for (int pos = 0; pos < NF; pos++) planes(pos, zbase, Pc{});
+
+    for (int sl = 0; sl < nslab; sl++) {
+        const bool first = sl == 0;
+        const int z0 = zs0 + sl * TZ;
+        const int w = (sl * TZ) % P;  // ring slot of plane z0 - 3
+        int zoff[7];
+#pragma unroll
+        for (int k = 0; k < 7; k++) {
+            int sk = w + lz + k;
+            sk -= sk >= P ? P : 0;
+            sk -= sk >= P ? P : 0;
+            zoff[k] = sk * SLOT + xyoff;
+        }
+        auto acc_for = [&](int pos) {
+            PlaneAcc<T, SY> a;
+#pragma unroll
+            for (int k = 0; k < 7; k++) a.zp[k] = ring(pos) + zoff[k];
+            return a;
+        };
+        auto wait_bar = [&](auto wc) {
+            constexpr int WN = decltype(wc)::value;
+            if (first) ring_barrier<0>();
+            else ring_barrier<WN>();
+        };
+        CellM<T> C;
+#pragma unroll
+        for (int f = 0; f < NF; f++) C.R[f] = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            C.B[a] = r.c.bext[a];
+            C.J[a] = T(0);
+            C.Bd[a] = 0.0;
+        }
+
+        // pass 0: ln rho; the last field's planes of this slab, the s-2 state
+        wait_bar(std::integral_constant<int, 5 * ND + NFC + ES>{});
+        if (!first) planes(6, z0 + TZ + 3 - TZ, TZc{});
+        if constexpr (OLDS) {
+            Old::copy(out[0], out[1], out[2], out[3], old_area, wave, lane, x0s, y0, z0, nx, ny, nz);
+            Old3::copy(out[4], out[5], out[6], out[6], old_area + 4 * NT, wave, lane, x0s, y0, z0, nx, ny, nz);
+        }
+        absorb_m<T, 0, DIAG>(C, acc_for(0), K, dc);
+
+        // pass 1: A_x; ln rho's next planes, this slab's forcing slots
+        wait_bar(std::integral_constant<int, 5 * ND + ES + NO>{});
+        planes(0, z0 + TZ + 3, TZc{});
+        if constexpr (STORE) Frc::copy(fblk, frc, lane, x0s, y0, z0, nx, ny, nz);
+        absorb_m<T, 4, DIAG>(C, acc_for(1), K, dc);
+
+        wait_bar(std::integral_constant<int, 5 * ND + ES + NO + NFC>{});
+        planes(1, z0 + TZ + 3, TZc{});
+        absorb_m<T, 5, DIAG>(C, acc_for(2), K, dc);
+
+        wait_bar(std::integral_constant<int, 5 * ND + ES + NO + NFC>{});
+        planes(2, z0 + TZ + 3, TZc{});
+        absorb_m<T, 6, DIAG>(C, acc_for(3), K, dc);
+
+        wait_bar(std::integral_constant<int, 5 * ND + ES + NO + NFC>{});
+        planes(3, z0 + TZ + 3, TZc{});
+        absorb_m<T, 1, DIAG>(C, acc_for(4), K, dc);
+
+        wait_bar(std::integral_constant<int, 5 * ND + ES + NO + NFC>{});
+        planes(4, z0 + TZ + 3, TZc{});
+        absorb_m<T, 2, DIAG>(C, acc_for(5), K, dc);
+
+        wait_bar(std::integral_constant<int, 5 * ND + NO + NFC>{});
+        planes(5, z0 + TZ + 3, TZc{});
+        absorb_m<T, 3, DIAG>(C, acc_for(6), K, dc);
+
+        // the end of the slab: deferred terms, forcing, RK update
+        wait_bar(std::integral_constant<int, 5 * ND>{});
+        const T *u = &C.v[1];
+#pragma unroll
+        for (int m = 0; m < 3; m++) C.R[1 + m] -= u[0] * C.du[m][0] + u[1] * C.du[m][1] + u[2] * C.du[m][2];
+        C.R[0] -= u[0] * C.g[0] + u[1] * C.g[1] + u[2] * C.g[2];
+        C.R[4] += u[1] * C.B[2] - u[2] * C.B[1];
+        C.R[5] += u[2] * C.B[0] - u[0] * C.B[2];
+        C.R[6] += u[0] * C.B[1] - u[1] * C.B[0];
+        const int gzc = z0 + lz;
+        const uint32_t gcell = (uint32_t)gxc + (uint32_t)nx * ((uint32_t)gyc + (uint32_t)ny * (uint32_t)gzc);
+        if constexpr (STORE) {
+            if (frc[6] != T(0)) {
+                constexpr int HV = Frc::HV;
+                const T *ex = frc + (HV + lx) * EPL, *ey = frc + (HV + TX + ly) * EPL,
+                        *ez = frc + (HV + TX + TY + lz) * EPL;
+                const T pr = ex[0] * ey[0] - ex[1] * ey[1], pi = ex[0] * ey[1] + ex[1] * ey[0];
+                const T cr = pr * ez[0] - pi * ez[1], ci = pr * ez[1] + pi * ez[0];
+#pragma unroll
+                for (int q = 0; q < 3; q++) C.R[1 + q] += frc[q] * cr + frc[3 + q] * ci;
+            }
+            const T bdt = r.c.bdt[SUB], brho = r.c.brho[SUB];
+#pragma unroll
+            for (int f = 0; f < NF; f++) {
+                T o;
+                if constexpr (SUB == 0) {
+                    o = C.v[f] + bdt * C.R[f];
+                } else {
+                    const T old = old_area[f * NT + tid];
+                    o = C.v[f] + brho * (C.v[f] - old) + bdt * C.R[f];
+                }
+                out[f][gcell] = o;
+            }
+        }
+        if constexpr (DIAG) {
+            const double bx = C.Bd[0] + dc.bext[0], by = C.Bd[1] + dc.bext[1], bz = C.Bd[2] + dc.bext[2];
+            const double ux = (double)C.v[1], uy = (double)C.v[2], uz = (double)C.v[3];
+            const double u2 = ux * ux + uy * uy + uz * uz;
+            acc[0] += bx * bx + by * by + bz * bz;
+            acc[1] += u2;
+            acc[2] += exp((double)C.v[0]) * u2;
+            acc[3] += (double)C.v[0];
+            acc[4] += bx;
+            acc[5] += by;
+            acc[6] += bz;
+            acc[7] = fmax(acc[7], u2);
+            bool ok = true;
+#pragma unroll
+            for (int f = 0; f < NF; f++) ok = ok && finite_v(C.v[f]);
+            acc[8] += ok ? 0.0 : 1.0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // no copy may still be writing into this work-group's LDS when it ends
+    ring_barrier<0>();
+    if constexpr (DIAG) {
+#pragma unroll
+        for (int q = 0; q < 9; q++) acc[q] = (q == 7) ? wave_reduce<true>(acc[q]) : wave_reduce<false>(acc[q]);
+        double *red = reinterpret_cast<double *>(old_area);
+        if (lane == 63) {
+#pragma unroll
+            for (int q = 0; q < 9; q++) red[wave * 9 + q] = acc[q];
+        }
+        __syncthreads();
+        if (tid < 9) {
+            double sum = red[tid];
+            for (int wv = 1; wv < NT / 64; wv++) sum = (tid == 7) ? fmax(sum, red[wv * 9 + tid]) : sum + red[wv * 9 + tid];
+            ((G<double> *)r.partials)[(size_t)te.tir * DIAGW + tid] = sum;
+        }
+    }
 }
 
 // Per-run reduction of the tile partials into one diagnostic record, in two launches

@@ -15,8 +15,9 @@ namespace mhd {
 struct Shape {
     int tx, ty, tz, cz;
     bool pipe;   // true: direct-to-LDS ring kernel (k_pipe); false: register-staged kernel (k_substep)
+    bool march;  // true: z-marching column kernel (k_march); tz is its slab depth
 };
-constexpr int NSHAPES = 12;
+constexpr int NSHAPES = 14;
 extern const Shape SHAPES[NSHAPES];
 
 // steps whose forcing blocks and diagnostic records are staged at once
@@ -36,6 +37,7 @@ struct mhd_ctx {
     int shape = 0;
     bool fit = false;        // halo box spans at most one period per axis (cheap wrap)
     int xs = 0;              // x offset of the tile grid (ring kernel)
+    int seg = 0;             // z-segment length of the marching kernel
     int ntiles = 0;
     int fstride = 0;
     bool owns = false;
@@ -97,5 +99,7 @@ template <typename T>
 hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int max_nb2, int step, hipStream_t st);
 int run_nb2(const mhd_params &p, int shape);
 int x_shift(const mhd_params &p, int shape);
+int march_segment(const mhd_params &p, int shape);
+int shape_fallback(int shape);
 
 }  // namespace mhd

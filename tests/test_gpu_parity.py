@@ -101,7 +101,7 @@ def test_config1_32cubed_every_step(mhd, prec):
             assert abs(rec[k] - ref[k]) <= tol * abs(ref[k]) + 1e-300, (n, k, rec[k], ref[k])
 
 
-@pytest.mark.parametrize("shape", range(12))
+@pytest.mark.parametrize("shape", range(14))
 def test_every_tile_shape_ragged_grid_fp64(mhd, shape):
     rp = mi.RunParams(20, 18, 13, nu=4e-3, eta=6e-3, dt=1e-3, precision=8, bext=(0.01, 0.0, -0.02))
     st = mi.noise_state(rp, 5 + shape, 0.2, 0.2, 0.2)
@@ -124,7 +124,7 @@ def test_tile_shapes_fp32(mhd, shape):
 
 
 @pytest.mark.parametrize("prec", [8, 4])
-@pytest.mark.parametrize("shape", range(6, 12))
+@pytest.mark.parametrize("shape", range(6, 14))
 def test_ring_shapes_wrap_once(mhd, shape, prec):
     """Ring kernels on a grid larger than their halo box (single-wrap offsets)."""
     rp = mi.RunParams(48, 40, 32, nu=3e-3, eta=2e-3, dt=1e-3, precision=prec)
@@ -134,6 +134,37 @@ def test_ring_shapes_wrap_once(mhd, shape, prec):
     want, scales = oracle_per_step(st, rp, recs)
     for n in range(2):
         check_step(got[n], want[n], scales[n], rp, f"ring shape {shape} fp{8 * prec} step {n + 1}")
+
+
+@pytest.mark.parametrize("prec", [8, 4])
+@pytest.mark.parametrize("shape", [12, 13])
+def test_march_shapes_several_slabs(mhd, shape, prec):
+    """z-marching kernel on 64x48x40: two z-segments of five slabs per column (the first
+    slab, steady slabs and the prefetch past a segment's end); every step and the
+    diagnostics of the shared input state against the oracle, then a diagnostics-only
+    launch on a later state."""
+    rp = mi.RunParams(64, 48, 40, nu=3e-3, eta=2e-3, dt=1e-3, precision=prec, bext=(0.0, 0.02, 0.0))
+    st = mi.noise_state(rp, 80 + shape, 0.2, 0.2, 0.2, dtype=_dtype(prec))
+    recs = mi.forcing_schedule(9, 3, 3.0, 0.05, 1.0)
+    got, diag = gpu_run(mhd, rp, st, recs, per_step=True, shape=shape)
+    want, scales = oracle_per_step(st, rp, recs)
+    for n in range(3):
+        check_step(got[n], want[n], scales[n], rp, f"march shape {shape} fp{8 * prec} step {n + 1}")
+    ref = oracle.diag(st.astype(np.float64), rp)
+    for k in ("em", "ek", "urms", "brms", "umax"):
+        assert abs(diag[0][k] - ref[k]) <= 1e-12 * abs(ref[k]), (k, diag[0][k], ref[k])
+    p = mhd.params_from(rp)
+    mhd.mhd_set_tile_shape(p, shape)
+    try:
+        with mhd.Run(p) as run:
+            run.set_state(got[-1])
+            mhd.mhd_reduce(run.h)
+            rec = run.diag()[-1]
+    finally:
+        mhd.mhd_set_tile_shape(p, -1)
+    ref = oracle.diag(got[-1].astype(np.float64), rp)
+    for k in ("em", "ek", "urms", "brms", "umax", "lnrho_mean"):
+        assert abs(rec[k] - ref[k]) <= 1e-12 * max(abs(ref[k]), 1e-300), (k, rec[k], ref[k])
 
 
 @pytest.mark.parametrize("n", [8, 9, 33])
