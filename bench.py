@@ -70,8 +70,9 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else 0.0
 
 
-def single_run(mhd, n, prec, warmup, steps, nu=4e-4):
-    """512^3 non-helical forced run from the Section 4 initial condition."""
+def single_run(mhd, n, prec, warmup, steps, nu=4e-4, keep=False):
+    """512^3 non-helical forced run from the Section 4 initial condition.  With keep,
+    the context stays alive and is returned as "handle" (the caller destroys it)."""
     p = mhd.make_params(n, nu=nu, eta=nu, dt=1e-3, precision=prec)
     h = mhd.mhd_create(p)
     try:
@@ -82,8 +83,12 @@ def single_run(mhd, n, prec, warmup, steps, nu=4e-4):
         kms, step_ms = mhd.mhd_step_timed(h, steps)
         diag = mhd.mhd_get_diag(h)
         tile = mhd.mhd_tile_config(p)
-    finally:
+    except BaseException:
         mhd.mhd_destroy(h)
+        raise
+    if not keep:
+        mhd.mhd_destroy(h)
+        h = None
     cells = float(n) ** 3
     ms = float(np.mean(step_ms))
     rate = 3.0 * cells / (ms * 1e-3)
@@ -98,7 +103,27 @@ def single_run(mhd, n, prec, warmup, steps, nu=4e-4):
         kernel_ms=dict(substep1=kms[0], substep2=kms[1], substep3=kms[2], finalize=kms[3]),
         substep_kernel_gbs=achieved, sub2_bytes=sub2_bytes, sub2_ms=kms[1],
         sub2_gbs=sub2_bytes / (kms[1] * 1e-3) / 1e9, tile=tile,
-        nonfinite=max(d["nonfinite"] for d in diag), ns_per_point_step=ms * 1e6 / cells)
+        nonfinite=max(d["nonfinite"] for d in diag), ns_per_point_step=ms * 1e6 / cells,
+        handle=h, steps_done=warmup + steps)
+
+
+def fp32_vs_fp64(mhd, h64, h32, n):
+    """Per-field difference of the FP32 run from the FP64 run after the same steps from
+    the same seeded state and forcing: max |f32 - f64| / max |f64| (ln rho, which starts
+    at 0, relative to max(max |f64|, 1e-12)).  Copies field by field on the device."""
+    import torch
+    out = {}
+    a = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    b = torch.empty(n ** 3, dtype=torch.float32, device="cuda")
+    for f, name in enumerate(mi.FIELD_NAMES):
+        mhd.mhd_sync(h64)
+        mhd.mhd_sync(h32)
+        mhd.mhd_get_field(h64, f, a)
+        mhd.mhd_get_field(h32, f, b)
+        torch.cuda.synchronize()
+        den = max(float(a.abs().max()), 1e-12)
+        out[name] = float((b.double() - a).abs().max()) / den
+    return out
 
 
 def shape_sweep(mhd, n, steps=3):
@@ -308,13 +333,21 @@ def main():
         sweep = shape_sweep(mhd, args.n)
 
     log(f"[bench] {args.n}^3 FP64: {args.warmup} warm-up + {args.steps} timed steps")
-    r64 = single_run(mhd, args.n, mhd.MHD_FP64, args.warmup, args.steps)
+    r64 = single_run(mhd, args.n, mhd.MHD_FP64, args.warmup, args.steps, keep=not args.no_fp32)
     log(f"[bench] FP64 {r64['cell_substeps_per_s']:.3e} cell-substeps/s, {r64['ms_per_step']:.2f} ms/step")
     r32 = None
+    fp32_err = None
     if not args.no_fp32:
         log(f"[bench] {args.n}^3 FP32")
-        r32 = single_run(mhd, args.n, mhd.MHD_FP32, args.warmup, args.steps)
+        r32 = single_run(mhd, args.n, mhd.MHD_FP32, args.warmup, args.steps, keep=True)
         log(f"[bench] FP32 {r32['cell_substeps_per_s']:.3e} cell-substeps/s, {r32['ms_per_step']:.2f} ms/step")
+        try:
+            fp32_err = fp32_vs_fp64(mhd, r64["handle"], r32["handle"], args.n)
+            log("[bench] FP32 vs FP64 after %d steps: " % r32["steps_done"]
+                + " ".join(f"{k}:{v:.1e}" for k, v in fp32_err.items()))
+        finally:
+            mhd.mhd_destroy(r64["handle"])
+            mhd.mhd_destroy(r32["handle"])
     ens = None
     if not args.no_ensemble:
         log("[bench] ensemble: 48 runs x %d steps" % args.ensemble_steps)
@@ -371,6 +404,7 @@ def main():
             "substep_kernel_gbs": r32["substep_kernel_gbs"], "sub2_gbs": r32["sub2_gbs"],
             "roofline_frac": r32["sub2_gbs"] / HBM_PEAK_GBS, "kernel_ms": r32["kernel_ms"],
             "traffic": stored_traffic(4, args.n, r32["tile"]),
+            "per_field_error_vs_fp64": fp32_err, "error_after_steps": r32["steps_done"],
             "tile": r32["tile"]},
         "ensemble": ens,
         "serving": srv,
