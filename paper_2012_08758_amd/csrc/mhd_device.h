@@ -147,6 +147,7 @@ struct Cells {
     T R[CZ][NF];        // right-hand side accumulators
     double Bd[CZ][3];   // FP64 curl, for the diagnostics
     T old[CZ][NF];      // state of substep s-2 at the cells (filled early by the ring kernel)
+    T pend[CZ][3];      // u-first order: d_y u_x, d_z u_x, d_z u_y until u_y / u_z are known
     bool have_old = false;
 };
 
@@ -176,9 +177,23 @@ __device__ __forceinline__ void pin(Cells<T, CZ> &C)
     }
 }
 
+template <typename T, int CZ>
+__device__ __forceinline__ void pin_pend(Cells<T, CZ> &C, int n)
+{
+#pragma unroll
+    for (int c = 0; c < CZ; c++)
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+            if (a < n) asm volatile("" : "+v"(C.pend[c][a]));
+}
+
 // Fold the derivatives of field F at this thread's cells into the accumulators.
 // Fields pass in the order ln rho, A_x, A_y, A_z, u_x, u_y, u_z.
-template <typename T, int F, int SY, int SZ, int CZ, bool DIAG>
+// UFIRST: the ring kernel's order ln rho, u_x, u_y, u_z, A_x, A_y, A_z, in which every
+// centre value comes from its own field's box: the advection products whose velocity
+// component has not passed yet are held as their derivative (pend) and completed in
+// the later u passes, and -u.grad ln rho is added once u_z has passed.
+template <typename T, int F, int SY, int SZ, int CZ, bool DIAG, bool UFIRST = false>
 __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&cidx)[CZ], const KRegs<T> &K,
                                        const DCoef &dc)
 {
@@ -190,7 +205,10 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
             C.g[c][0] = sd1(s, s0, K.ih1[0]);
             C.g[c][1] = sd1(s, s1, K.ih1[1]);
             C.g[c][2] = sd1(s, s2, K.ih1[2]);
-            C.R[c][0] -= C.v[c][1] * C.g[c][0] + C.v[c][2] * C.g[c][1] + C.v[c][3] * C.g[c][2];
+            if constexpr (UFIRST)
+                C.v[c][0] = s[0];
+            else
+                C.R[c][0] -= C.v[c][1] * C.g[c][0] + C.v[c][2] * C.g[c][1] + C.v[c][3] * C.g[c][2];
             C.R[c][1] -= K.cs2 * C.g[c][0];
             C.R[c][2] -= K.cs2 * C.g[c][1];
             C.R[c][3] -= K.cs2 * C.g[c][2];
@@ -246,7 +264,25 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
             const T *g = C.g[c], *u = &C.v[c][1];
             // viscous: nu lap u_m + nu/3 d_m d_m u_m; advection; strain row m
             T rm = K.nu * lap + K.nu3 * d2m;
-            rm -= u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+            if constexpr (UFIRST) {
+                C.v[c][F] = s[0];
+                if constexpr (m == 0) {
+                    rm -= u[0] * du[0];
+                    C.pend[c][0] = du[1];
+                    C.pend[c][1] = du[2];
+                } else if constexpr (m == 1) {
+                    C.R[c][1] -= u[1] * C.pend[c][0];
+                    rm -= u[0] * du[0] + u[1] * du[1];
+                    C.pend[c][2] = du[2];
+                } else {
+                    C.R[c][1] -= u[2] * C.pend[c][1];
+                    C.R[c][2] -= u[2] * C.pend[c][2];
+                    rm -= u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+                    C.R[c][0] -= u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+                }
+            } else {
+                rm -= u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+            }
             rm += K.nu * (du[0] * g[0] + du[1] * g[1] + du[2] * g[2]);
             C.R[c][1 + m] += rm;
             C.R[c][0] -= du[m];
@@ -677,10 +713,11 @@ constexpr int pipe_lds_bytes()
 // Every read of the pipeline is a direct-to-LDS copy, which the compiler's wait
 // analysis does not see; a register load issued before such copies would get a
 // full drain (vmcnt(0)) in front of its first use, stalling the prefetch.  So the
-// centre values, the forcing slots and the s-2 state also travel through LDS, in
-// ring buffers that are free at that moment, and every wait is explicit:
-//   start: forcing slots and centre values -> buffer 2, field 0 -> 0, field 4 -> 1
-//   pass 0: read centre and forcing from buffer 2, barrier, field 5 -> 2
+// forcing slots and the s-2 state also travel through LDS, in ring buffers that are
+// free at that moment, the centre values are read from the fields' own boxes, and
+// every wait is explicit:
+//   start: forcing slots -> buffer 2, field 0 -> 0, field 1 -> 1
+//   pass 0: forcing from buffer 2, barrier, field 2 -> 2
 //   passes 1-4: the next field two ahead; pass 5: s-2 state of ln rho, u -> 1;
 //   pass 6: s-2 state of A -> 2; then the update reads them from LDS.
 template <typename T, int TX, int TY, int TZ, int CZ, int SUB, bool DIAG, bool STORE, int WPE, bool FIT>
@@ -697,15 +734,13 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     constexpr int SY = XW, SZ = XW * YW;
     constexpr int ZS = TZ / CZ;
     constexpr int NCELL = TX * TY * TZ;
-    constexpr int FOFF = 64 * EPL;  // centre values follow the forcing slots in buffer 2
-    using Cen = Interior<T, TX, TY, TZ, NT, 4>;
     using Old1 = Interior<T, TX, TY, TZ, NT, 4>;
     using Old2 = Interior<T, TX, TY, TZ, NT, 3>;
     using Frc = ForcingSlots<T, TX, TY, TZ>;
     static_assert(XW % EPL == 0 && TX % EPL == 0, "rows must hold whole vectors");
     static_assert(NT % 64 == 0, "whole waves");
-    static_assert(FOFF + 4 * NCELL <= BUF, "centre values and forcing slots fit one ring buffer");
-    static_assert(Cen::NI + 2 * NV < 64 && Old1::NI + Old2::NI < 64, "vmcnt is a 6-bit counter");
+    static_assert(64 * EPL <= BUF && 4 * NCELL <= BUF, "forcing slots and the s-2 state fit a ring buffer");
+    static_assert(2 * NV + 1 < 64 && Old1::NI + Old2::NI < 64, "vmcnt is a 6-bit counter");
     static_assert(!(DIAG && SUB != 0), "diagnostics are taken in substep 0 only");
 
     __shared__ __align__(16) T lds[3][BUF];
@@ -773,13 +808,13 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     K.load(r.c);
     const DCoef &dc = r.dc;
 
-    // fields pass in the order ln rho, A_x, A_y, A_z, u_x, u_y, u_z; field k of that
-    // order lives in ring buffer k % 3 and is requested two passes ahead
+    // fields pass in memory order ln rho, u_x, u_y, u_z, A_x, A_y, A_z (field k lives in
+    // ring buffer k % 3 and is requested two passes ahead); each centre value comes
+    // from its own field's box
     if constexpr (STORE)
         Frc::copy((const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride, lds[2], lane, x0s, y0, z0, nx, ny, nz);
-    Cen::copy(in[0], in[1], in[2], in[3], lds[2] + FOFF, wave, lane, x0s, y0, z0, nx, ny, nz);
     ring_copy<T, NV, NT, EPL>(in[0], lds[0], voff, wave);
-    ring_copy<T, NV, NT, EPL>(in[4], lds[1], voff, wave);
+    ring_copy<T, NV, NT, EPL>(in[1], lds[1], voff, wave);
 
     Cells<T, CZ> C;
     ring_barrier<NV>();
@@ -789,62 +824,54 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         for (int f = 0; f < NF; f++) C.R[c][f] = T(0);
 #pragma unroll
         for (int a = 0; a < 3; a++) { C.B[c][a] = r.c.bext[a]; C.J[c][a] = T(0); C.Bd[c][a] = 0.0; }
-#pragma unroll
-        for (int f = 0; f < 4; f++) C.v[c][f] = lds[2][FOFF + f * NCELL + icell[c]];
     }
     if constexpr (STORE) Frc::template add<CZ, ZS>(C, lds[2], lx, ly, lz0);
     pin(C);
-    lds_barrier();  // buffer 2 is read out
+    lds_barrier();  // buffer 2 (forcing slots) is read out
+    ring_copy<T, NV, NT, EPL>(in[2], lds[2], voff, wave);
+    absorb<T, 0, SY, SZ, CZ, DIAG, true>(C, lds[0], cidx, K, dc);
+
+    ring_barrier<NV>();
+    ring_copy<T, NV, NT, EPL>(in[3], lds[0], voff, wave);
+    absorb<T, 1, SY, SZ, CZ, DIAG, true>(C, lds[1], cidx, K, dc);
+    pin_pend(C, 2);
+
+    ring_barrier<NV>();
+    ring_copy<T, NV, NT, EPL>(in[4], lds[1], voff, wave);
+    absorb<T, 2, SY, SZ, CZ, DIAG, true>(C, lds[2], cidx, K, dc);
+    pin_pend(C, 3);
+
+    ring_barrier<NV>();
     ring_copy<T, NV, NT, EPL>(in[5], lds[2], voff, wave);
-    absorb<T, 0, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+    absorb<T, 3, SY, SZ, CZ, DIAG, true>(C, lds[0], cidx, K, dc);
 
     ring_barrier<NV>();
     ring_copy<T, NV, NT, EPL>(in[6], lds[0], voff, wave);
-    absorb<T, 4, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
+    absorb<T, 4, SY, SZ, CZ, DIAG, true>(C, lds[1], cidx, K, dc);
 
-    if constexpr (STORE) {
-        ring_barrier<NV>();
-        ring_copy<T, NV, NT, EPL>(in[1], lds[1], voff, wave);
-        absorb<T, 5, SY, SZ, CZ, DIAG>(C, lds[2], cidx, K, dc);
+    ring_barrier<NV>();
+    if constexpr (STORE && SUB != 0)  // buffer 1 (A_x) is read out: the s-2 state of ln rho, u
+        Old1::copy(out[0], out[1], out[2], out[3], lds[1], wave, lane, x0s, y0, z0, nx, ny, nz);
+    absorb<T, 5, SY, SZ, CZ, DIAG, true>(C, lds[2], cidx, K, dc);
 
-        ring_barrier<NV>();
-        ring_copy<T, NV, NT, EPL>(in[2], lds[2], voff, wave);
-        absorb<T, 6, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
-
-        ring_barrier<NV>();
-        ring_copy<T, NV, NT, EPL>(in[3], lds[0], voff, wave);
-        absorb<T, 1, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
-
-        ring_barrier<NV>();
-        if constexpr (SUB != 0)  // buffer 1 (u_x) is read out: the s-2 state of ln rho, u
-            Old1::copy(out[0], out[1], out[2], out[3], lds[1], wave, lane, x0s, y0, z0, nx, ny, nz);
-        absorb<T, 2, SY, SZ, CZ, DIAG>(C, lds[2], cidx, K, dc);
-
-        if constexpr (SUB != 0) {
-            ring_barrier<Old1::NI>();
-            // buffer 2 (u_y) is read out: the s-2 state of A
-            Old2::copy(out[4], out[5], out[6], out[6], lds[2], wave, lane, x0s, y0, z0, nx, ny, nz);
-        } else {
-            ring_barrier<0>();
-        }
-        absorb<T, 3, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
-        if constexpr (SUB != 0) {
-            ring_barrier<0>();
-#pragma unroll
-            for (int c = 0; c < CZ; c++) {
-#pragma unroll
-                for (int f = 0; f < 4; f++) C.old[c][f] = lds[1][f * NCELL + icell[c]];
-#pragma unroll
-                for (int f = 4; f < NF; f++) C.old[c][f] = lds[2][(f - 4) * NCELL + icell[c]];
-            }
-            C.have_old = true;
-        }
+    if constexpr (STORE && SUB != 0) {
+        ring_barrier<Old1::NI>();
+        // buffer 2 (A_y) is read out: the s-2 state of A
+        Old2::copy(out[4], out[5], out[6], out[6], lds[2], wave, lane, x0s, y0, z0, nx, ny, nz);
     } else {
-        ring_barrier<NV>();
-        absorb<T, 5, SY, SZ, CZ, DIAG>(C, lds[2], cidx, K, dc);
-
         ring_barrier<0>();
-        absorb<T, 6, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+    }
+    absorb<T, 6, SY, SZ, CZ, DIAG, true>(C, lds[0], cidx, K, dc);
+    if constexpr (STORE && SUB != 0) {
+        ring_barrier<0>();
+#pragma unroll
+        for (int c = 0; c < CZ; c++) {
+#pragma unroll
+            for (int f = 0; f < 4; f++) C.old[c][f] = lds[1][f * NCELL + icell[c]];
+#pragma unroll
+            for (int f = 4; f < NF; f++) C.old[c][f] = lds[2][(f - 4) * NCELL + icell[c]];
+        }
+        C.have_old = true;
     }
     __builtin_amdgcn_sched_barrier(0);
     finish<T, CZ, NT, SUB, DIAG, STORE, false>(C, r, te, r.c, dc, inside, gcell, gpos, out,
