@@ -230,7 +230,7 @@ def ensemble(mhd, nsteps=500, alone_steps=None):
                 speedup_vs_alone=t_alone / wall, nonfinite_runs=int(bad))
 
 
-def serving(mhd, nruns=40, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tick=5):
+def serving(mhd, nruns=40, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tick=10):
     """First `nruns` arrivals of the Poisson trace (rate 4/s, N in {32,64,128,256}, FP32,
     `nsteps` steps each), served with continuous batching; the FCFS one-at-a-time
     baseline uses measured standalone service times on the same arrivals."""
@@ -252,15 +252,21 @@ def serving(mhd, nruns=40, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tick
         st = mhd.mhd_server_stats_get(srv)
     finally:
         mhd.mhd_server_destroy(srv)
-    # baseline: each distinct run size alone, then FCFS over the same arrivals
+    # baseline: each distinct run size alone with the plain solver (set-up, seed field,
+    # steps, tear-down, as a one-by-one user would run it), then FCFS over the same
+    # arrivals
     service = {}
     step_ms = {}
+    setup_s = {}
     for n in sorted({r["n"] for r in trace}):
         p = mhd.make_params(n, nu=1e-3, eta=1e-3, dt=1e-3, precision=4)
+        t_set = time.perf_counter()
         h = mhd.mhd_create(p)
         try:
             mhd.mhd_init_seed(h, 0, 1e-5)
             mhd.mhd_set_forcing_random(h, 3.0, 0.02, 0.0, 0)
+            mhd.mhd_sync(h)
+            t_set = time.perf_counter() - t_set
             mhd.mhd_step(h, 5)
             mhd.mhd_sync(h)
             m = min(nsteps, 200)
@@ -268,9 +274,12 @@ def serving(mhd, nruns=40, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tick
             mhd.mhd_step(h, m)
             mhd.mhd_sync(h)
             step_ms[n] = (time.perf_counter() - ta) * 1e3 / m
-            service[n] = step_ms[n] * nsteps / 1e3
         finally:
+            td = time.perf_counter()
             mhd.mhd_destroy(h)
+            t_set += time.perf_counter() - td
+        setup_s[n] = t_set
+        service[n] = step_ms[n] * nsteps / 1e3 + t_set
     free_at, fin, lat = 0.0, [], []
     for r in trace:
         start = max(free_at, r["arrival"])
@@ -287,7 +296,8 @@ def serving(mhd, nruns=40, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tick
                 hbm_peak_gb=st.hbm_peak / 2 ** 30, cell_substeps_per_s=st.cell_substeps / max(st.busy_s, 1e-9),
                 fcfs_alone=dict(makespan_s=fcfs_makespan, runs_per_hour=nruns / fcfs_makespan * 3600.0,
                                 e2e_p50_s=pct(fin, 50), e2e_p99_s=pct(fin, 99),
-                                step_latency_ms={str(k): v for k, v in step_ms.items()}))
+                                step_latency_ms={str(k): v for k, v in step_ms.items()},
+                                setup_teardown_s={str(k): v for k, v in setup_s.items()}))
 
 
 def main():

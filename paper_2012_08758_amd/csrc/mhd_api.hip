@@ -857,46 +857,64 @@ mhd_status ctx_step(mhd_ctx *c, int64_t n)
 }
 
 // Initial condition on the host, generated in parallel slices.
+// The seed field of A (three fields, x fastest), generated on the host: SplitMix64
+// counters of stream 100 + field, Box-Muller pairs.  Pure host work, so a caller can
+// run it while the device is busy.
+void init_noise_host(const mhd_params &p, uint64_t seed, double amp, std::vector<char> &out)
+{
+    const size_t n = (size_t)p.nx * p.ny * p.nz;
+    const int prec = p.precision;
+    out.resize(3 * n * prec);
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    for (int f = 4; f < NF; f++) {
+        char *dst = out.data() + (size_t)(f - 4) * n * prec;
+        const uint64_t key = sm_key(seed, 100 + f);
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nth; t++) {
+            th.emplace_back([&, t]() {
+                const size_t npair = (n + 1) / 2;
+                const size_t lo = npair * t / nth, hi = npair * (t + 1) / nth;
+                for (size_t pi = lo; pi < hi; pi++) {
+                    const double u1 = sm_unif(key, 2 * pi), u2 = sm_unif(key, 2 * pi + 1);
+                    const double r = std::sqrt(-2.0 * std::log1p(-u1));
+                    const double z0 = amp * (r * std::cos(2.0 * M_PI * u2));
+                    const double z1 = amp * (r * std::sin(2.0 * M_PI * u2));
+                    const size_t i0 = 2 * pi, i1 = 2 * pi + 1;
+                    if (prec == MHD_FP64) {
+                        ((double *)dst)[i0] = z0;
+                        if (i1 < n) ((double *)dst)[i1] = z1;
+                    } else {
+                        ((float *)dst)[i0] = (float)z0;
+                        if (i1 < n) ((float *)dst)[i1] = (float)z1;
+                    }
+                }
+            });
+        }
+        for (auto &x : th) x.join();
+    }
+}
+
+// ln rho = 0, u = 0, A = the given seed field, into the current buffer set
+mhd_status ctx_upload_seed(mhd_ctx *c, const std::vector<char> &noise)
+{
+    const size_t bytes = c->ncell * c->p.precision;
+    if (noise.size() != 3 * bytes) return fail(MHD_E_INVALID, "seed field has the wrong size");
+    for (int f = 0; f < 4; f++)
+        if (hipMemsetAsync(c->bufs[c->parity][f], 0, bytes, c->stream) != hipSuccess)
+            return fail(MHD_E_DEVICE, "clearing the initial condition failed");
+    for (int f = 4; f < NF; f++)
+        if (hipMemcpyAsync(c->bufs[c->parity][f], noise.data() + (size_t)(f - 4) * bytes, bytes,
+                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return fail(MHD_E_DEVICE, "uploading the initial condition failed");
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(MHD_E_DEVICE, "uploading the initial condition failed");
+    return MHD_OK;
+}
+
 mhd_status ctx_init_seed(mhd_ctx *c, uint64_t seed, double amp)
 {
-    const size_t n = c->ncell;
-    const int prec = c->p.precision;
-    std::vector<char> host(n * prec);
-    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    for (int f = 0; f < NF; f++) {
-        if (f < 4) {
-            std::memset(host.data(), 0, host.size());
-        } else {
-            const uint64_t key = sm_key(seed, 100 + f);
-            std::vector<std::thread> th;
-            for (unsigned t = 0; t < nth; t++) {
-                th.emplace_back([&, t]() {
-                    const size_t npair = (n + 1) / 2;
-                    const size_t lo = npair * t / nth, hi = npair * (t + 1) / nth;
-                    for (size_t pi = lo; pi < hi; pi++) {
-                        const double u1 = sm_unif(key, 2 * pi), u2 = sm_unif(key, 2 * pi + 1);
-                        const double r = std::sqrt(-2.0 * std::log1p(-u1));
-                        const double z0 = amp * (r * std::cos(2.0 * M_PI * u2));
-                        const double z1 = amp * (r * std::sin(2.0 * M_PI * u2));
-                        const size_t i0 = 2 * pi, i1 = 2 * pi + 1;
-                        if (prec == MHD_FP64) {
-                            ((double *)host.data())[i0] = z0;
-                            if (i1 < n) ((double *)host.data())[i1] = z1;
-                        } else {
-                            ((float *)host.data())[i0] = (float)z0;
-                            if (i1 < n) ((float *)host.data())[i1] = (float)z1;
-                        }
-                    }
-                });
-            }
-            for (auto &x : th) x.join();
-        }
-        if (hipMemcpyAsync(c->bufs[c->parity][f], host.data(), host.size(), hipMemcpyHostToDevice, c->stream) !=
-                hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess)
-            return fail(MHD_E_DEVICE, "uploading the initial condition failed");
-    }
-    return MHD_OK;
+    std::vector<char> noise;
+    init_noise_host(c->p, seed, amp, noise);
+    return ctx_upload_seed(c, noise);
 }
 
 }  // namespace mhd

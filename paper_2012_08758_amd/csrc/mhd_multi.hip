@@ -311,8 +311,11 @@ void mhd_server::loop()
 {
     bool set_changed = true;
     std::vector<mhd_ctx *> ctxs;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const bool have_ev = hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
     while (!stop_req.load()) {
-        // admission (FIFO) by footprint and free slots
+        // admission (FIFO) by footprint and free slots; admitted runs are prepared while
+        // the current tick runs on the device and join from the next tick on
         std::vector<Request *> admit;
         {
             std::unique_lock<std::mutex> lk(mu);
@@ -329,11 +332,52 @@ void mhd_server::loop()
                 admit.push_back(r);
             }
         }
-        for (Request *r : admit) {
+        std::vector<Request *> act;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (int64_t id : active) act.push_back(reqs[id].get());
+        }
+        // 1. the tick of the active set goes to the device (replayed as a captured graph
+        //    while the set is unchanged; rebuilt after an admission or a retirement)
+        int64_t k = 0;
+        mhd_status st = MHD_OK;
+        if (!act.empty()) {
+            if (set_changed) {
+                ctxs.clear();
+                for (Request *r : act) ctxs.push_back(r->ctx);
+                if (mr.build(ctxs) != MHD_OK) {
+                    worker_error = g_err;
+                    break;
+                }
+                set_changed = false;
+            }
+            k = steps_per_tick;
+            for (Request *r : act) k = std::min<int64_t>(k, r->nsteps - r->steps_done);
+            if (have_ev) (void)hipEventRecord(ev0, mr.stream);
+            st = mr.run(k, true);
+            if (have_ev) (void)hipEventRecord(ev1, mr.stream);
+        }
+        const double ta = now();
+        // 2. meanwhile, on the host: the seed fields of the admitted runs
+        std::vector<std::vector<char>> noise(admit.size());
+        for (size_t i = 0; i < admit.size(); i++) init_noise_host(admit[i]->p, admit[i]->seed, admit[i]->a_noise, noise[i]);
+        // 3. the end of the tick
+        if (st == MHD_OK && !act.empty() && hipStreamSynchronize(mr.stream) != hipSuccess)
+            st = fail(MHD_E_DEVICE, "device error in tick");
+        const double tb = now();
+        if (st != MHD_OK) {
+            worker_error = g_err;
+            break;
+        }
+        float tick_ms = (float)((tb - ta) * 1e3);
+        if (have_ev && !act.empty()) (void)hipEventElapsedTime(&tick_ms, ev0, ev1);
+        // 4. device state of the admitted runs
+        for (size_t i = 0; i < admit.size(); i++) {
+            Request *r = admit[i];
             mhd_ctx *c = new mhd_ctx();
-            mhd_status st = ctx_init(c, &r->p, mr.stream, nullptr, -1);
-            if (st == MHD_OK) st = ctx_init_seed(c, r->seed, r->a_noise);
-            if (st == MHD_OK) {
+            mhd_status st2 = ctx_init(c, &r->p, mr.stream, nullptr, -1);
+            if (st2 == MHD_OK) st2 = ctx_upload_seed(c, noise[i]);
+            if (st2 == MHD_OK) {
                 c->fmode = 2;
                 c->kf = r->kf;
                 c->f0 = r->f0;
@@ -342,7 +386,7 @@ void mhd_server::loop()
                 c->in_batch = true;
             }
             std::lock_guard<std::mutex> lk(mu);
-            if (st != MHD_OK) {
+            if (st2 != MHD_OK) {
                 ctx_release(c);
                 delete c;
                 r->state = MHD_RUN_FAILED;
@@ -360,31 +404,7 @@ void mhd_server::loop()
             n_adm++;
             set_changed = true;
         }
-        std::vector<Request *> act;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            for (int64_t id : active) act.push_back(reqs[id].get());
-        }
         if (act.empty()) continue;
-        if (set_changed) {
-            ctxs.clear();
-            for (Request *r : act) ctxs.push_back(r->ctx);
-            if (mr.build(ctxs) != MHD_OK) {
-                worker_error = g_err;
-                break;
-            }
-            set_changed = false;
-        }
-        int64_t k = steps_per_tick;
-        for (Request *r : act) k = std::min<int64_t>(k, r->nsteps - r->steps_done);
-        const double ta = now();
-        mhd_status st = mr.run(k, false);
-        if (st == MHD_OK && hipStreamSynchronize(mr.stream) != hipSuccess) st = fail(MHD_E_DEVICE, "device error in tick");
-        const double tb = now();
-        if (st != MHD_OK) {
-            worker_error = g_err;
-            break;
-        }
         double cells = 0;
         for (Request *r : act) cells += (double)r->ctx->ncell;
         // a run whose state went non-finite is evicted at the tick where it shows
@@ -397,9 +417,9 @@ void mhd_server::loop()
         {
             std::lock_guard<std::mutex> lk(mu);
             ticks++;
-            busy_s += tb - ta;
+            busy_s += tick_ms * 1e-3;
             cell_substeps += 3.0 * (double)k * cells;
-            const double per = (tb - ta) * 1e3 / (double)k;
+            const double per = tick_ms / (double)k;
             for (Request *r : act) {
                 r->steps_done += k;
                 for (int64_t q = 0; q < k; q++) step_lat_ms.push_back(per);
@@ -438,6 +458,8 @@ void mhd_server::loop()
         }
         if (!finished.empty()) cv.notify_all();
     }
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
     running.store(false);
     cv.notify_all();
 }
