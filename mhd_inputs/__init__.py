@@ -162,6 +162,7 @@ class RunParams:
     lz: float = TWO_PI
     bext: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     precision: int = 8  # bytes per value: 8 = FP64, 4 = FP32
+    upwind: float = 0.0  # upwinding coefficient of the continuity advection (0: off, 1: full)
 
     @property
     def ncell(self) -> int:

@@ -40,7 +40,7 @@ class _Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pad", C.c_int32),
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
                 ("cs", C.c_double), ("nu", C.c_double), ("eta", C.c_double), ("dt", C.c_double),
-                ("bext", C.c_double * 3)]
+                ("bext", C.c_double * 3), ("upwind", C.c_double)]
 
 
 class _Forcing(C.Structure):
@@ -87,6 +87,7 @@ def _params(p) -> _Params:
     q.cs, q.nu, q.eta, q.dt = p.cs, p.nu, p.eta, p.dt
     for c in range(3):
         q.bext[c] = p.bext[c]
+    q.upwind = float(getattr(p, "upwind", 0.0))
     return q
 
 

@@ -27,7 +27,12 @@
  *   - mixed derivatives use the diagonal stencil drawn in Fig. stencils.
  *   - j = grad(div A) - lap A, written with the same second-derivative stencils; the
  *     d_i d_i A_i term appears in both parts and cancels identically, so it is left out.
- *   - upwinding of the continuity equation (Section 4) is not applied.
+ *   - upwinding of the continuity equation (Section 4, after the fifth-order scheme
+ *     it cites): off unless the run's upwind coefficient c is set; then each
+ *     advective product u_a d_a ln(rho) is taken with the fifth-order stencil biased
+ *     against the flow, which equals the central sixth-order product minus
+ *     |u_a| delta6_a ln(rho) / (60 h_a), delta6 the seven-point sixth difference; c
+ *     scales that correction (c = 1: full upwinding).
  *   - an optional uniform field B_ext is added to B (zero unless set).
  *   - mu0 = 1, rho = exp(ln rho).
  *
@@ -51,6 +56,7 @@ typedef struct {
     double lx, ly, lz;
     double cs, nu, eta, dt;
     double bext[3];
+    double upwind;       /* upwinding coefficient of the continuity advection (0: off) */
 } ora_params;
 
 typedef struct {
@@ -95,6 +101,20 @@ static double d1(const view *v, int fld, int i, int j, int l, int a, double h)
         s += c[m] * (fp - fm);
     }
     return s / h;
+}
+
+/* Seven-point sixth difference along axis a: sum_m (-1)^(m+3) binom(6, m+3) f_m,
+ * i.e. h^6 times the sixth derivative to leading order. */
+static double d6(const view *v, int fld, int i, int j, int l, int a)
+{
+    static const double c[4] = {-20.0, 15.0, -6.0, 1.0};
+    double s = c[0] * at(v, fld, i, j, l);
+    for (int m = 1; m <= 3; m++) {
+        double fp = at(v, fld, i + m * AX[a][0], j + m * AX[a][1], l + m * AX[a][2]);
+        double fm = at(v, fld, i - m * AX[a][0], j - m * AX[a][1], l - m * AX[a][2]);
+        s += c[m] * (fp + fm);
+    }
+    return s;
 }
 
 /* Sixth-order central second derivative along axis a (exact for degree <= 7). */
@@ -224,11 +244,18 @@ static void rhs_cell(const view *v, const ora_params *p, const ora_forcing *fr,
     double cs2 = p->cs * p->cs;
 
     double ugl = u[0] * glnr[0] + u[1] * glnr[1] + u[2] * glnr[2];
-    R[0] = -ugl - divu;
+    /* upwinding: -(u_a d_a lnr)_upwind = -u_a d_a lnr + |u_a| delta6_a lnr / (60 h_a) */
+    double upw = 0.0;
+    if (p->upwind != 0.0) {
+        for (int a = 0; a < 3; a++) upw += fabs(u[a]) * d6(v, 0, i, j, l, a) / (60.0 * h[a]);
+        upw *= p->upwind;
+    }
+    R[0] = -ugl - divu + upw;
     if (tabs) {
         for (int t = 0; t < NF * NTERM; t++) tabs[t] = 0.0;
         tabs[0] = fabs(ugl);
         tabs[1] = fabs(du[0][0]) + fabs(du[1][1]) + fabs(du[2][2]);
+        tabs[2] = fabs(upw);
     }
     for (int c = 0; c < 3; c++) {
         double adv = u[0] * du[c][0] + u[1] * du[c][1] + u[2] * du[c][2];

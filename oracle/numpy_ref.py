@@ -40,7 +40,19 @@ def central_weights(order: int, radius: int = 3):
     return dict(zip(offs, _solve_exact(rows, rhs)))
 
 
+def one_sided_weights(lo: int, hi: int):
+    """First-derivative weights on offsets lo..hi (6 points: exact to degree 5)."""
+    offs = list(range(lo, hi + 1))
+    rows = [[Fraction(m) ** q / math.factorial(q) for m in offs] for q in range(len(offs))]
+    rhs = [1 if q == 1 else 0 for q in range(len(offs))]
+    return dict(zip(offs, _solve_exact(rows, rhs)))
+
+
 W1 = {m: float(w) for m, w in central_weights(1).items()}
+# fifth-order upwind-biased first derivatives: for flow in +a the stencil leans back
+# (offsets -3..2), for flow in -a forward (-2..3)
+WUP_POS = {m: float(w) for m, w in one_sided_weights(-3, 2).items()}
+WUP_NEG = {m: float(w) for m, w in one_sided_weights(-2, 3).items()}
 W2 = {m: float(w) for m, w in central_weights(2).items()}
 
 
@@ -127,6 +139,15 @@ def rhs(state, p, rec):
     rho_inv = np.exp(-lnr)
     R = np.empty_like(state)
     R[0] = -(u[0] * glnr[0] + u[1] * glnr[1] + u[2] * glnr[2]) - divu
+    c = float(getattr(p, "upwind", 0.0))
+    if c != 0.0:
+        # the advective products with the upwind-biased stencils, blended by c
+        up = np.zeros_like(lnr)
+        for a in range(3):
+            dpos = sum(w * _shift(lnr, _AX[a], m) for m, w in WUP_POS.items()) / h[a]
+            dneg = sum(w * _shift(lnr, _AX[a], m) for m, w in WUP_NEG.items()) / h[a]
+            up += u[a] * np.where(u[a] > 0, dpos, dneg)
+        R[0] = -(1.0 - c) * (u[0] * glnr[0] + u[1] * glnr[1] + u[2] * glnr[2]) - c * up - divu
     jxB = np.cross(np.stack(J), np.stack(B), axis=0)
     uxB = np.cross(u, np.stack(B), axis=0)
     for c in range(3):

@@ -430,6 +430,69 @@ def test_c_oracle_matches_independent_numpy_brute_force_8cubed():
     assert np.max(np.abs(s1 - s2)) <= 1e-13 * np.max(np.abs(s1))
 
 
+# ------------------------------------------------------------------ upwinding (Section 4)
+
+@pytest.mark.parametrize("c", [1.0, 0.4])
+def test_upwinding_matches_one_sided_fifth_order_stencils(c):
+    """The C oracle's correction form against the NumPy reference, which takes each
+    advective product with the six-point stencil (derived from the Taylor conditions)
+    that leans against the flow; random velocities of both signs, ragged grid."""
+    p = _p(9, 8, 10, nu=5e-3, eta=7e-3, dt=1e-3, upwind=c)
+    st = mi.noise_state(p, 41, 0.3, 0.6, 0.3)
+    rec = mi.forcing_schedule(2, 1, 3.0, 0.02, 0.3)[0]
+    R, _ = oracle.rhs(st, p, rec)
+    R2 = numpy_ref.rhs(st, p, rec)
+    assert np.max(np.abs(R[0] - R2[0])) <= 1e-13 * np.max(np.abs(R[0]))
+    assert np.max(np.abs(R[1:] - R2[1:])) <= 1e-13 * np.max(np.abs(R[1:]))
+    q = _p(9, 8, 10, nu=5e-3, eta=7e-3, dt=1e-3)
+    R0, _ = oracle.rhs(st, q, rec)
+    assert np.max(np.abs(R[0] - R0[0])) > 1e-6 * np.max(np.abs(R0[0]))  # the term is there
+    assert np.array_equal(R[1:], R0[1:])                                 # and nowhere else
+
+
+def test_upwinding_of_a_single_mode_has_the_sixth_difference_symbol():
+    """Uniform u, ln rho = eps sin(k.x): the added term is -|u_a| 64 sin^6(k_a h/2) / (60 h)
+    times ln rho per axis (a damping), and it is zero when u = 0."""
+    n, eps = 16, 1e-3
+    p = _p(n, upwind=1.0)
+    X, Y, Z = _coords(p)
+    k = (2, 3, 1)
+    u = (0.7, -0.4, 0.25)
+    lnr = eps * np.sin(k[0] * X + k[1] * Y + k[2] * Z)
+    st = np.zeros((7,) + X.shape)
+    st[0] = lnr
+    for a in range(3):
+        st[1 + a] = u[a]
+    R, _ = oracle.rhs(st, p, NOFORCE)
+    R0, _ = oracle.rhs(st, _p(n), NOFORCE)
+    h = TWO_PI / n
+    sym = -sum(abs(u[a]) * 64.0 * math.sin(k[a] * h / 2) ** 6 / (60.0 * h) for a in range(3))
+    assert np.max(np.abs((R[0] - R0[0]) - sym * lnr)) <= 1e-12 * eps
+    st[1:4] = 0.0
+    R, _ = oracle.rhs(st, p, NOFORCE)
+    assert np.max(np.abs(R[0])) == 0.0
+
+
+def test_upwinding_correction_vanishes_at_fifth_order():
+    ratios = []
+    prev = None
+    for n in (24, 48):
+        p = _p(n, upwind=1.0)
+        X, Y, Z = _coords(p)
+        st = np.zeros((7,) + X.shape)
+        st[0] = 0.1 * np.sin(X) * np.cos(2 * Y + Z)
+        st[1] = 0.3 * np.cos(Y)
+        st[2] = -0.2 * np.sin(Z + X)
+        st[3] = 0.1
+        R, _ = oracle.rhs(st, p, NOFORCE)
+        R0, _ = oracle.rhs(st, _p(n), NOFORCE)
+        e = np.max(np.abs(R[0] - R0[0]))
+        if prev is not None:
+            ratios.append(prev / e)
+        prev = e
+    assert 28.0 < ratios[0] < 36.0, ratios  # 2^5 = 32
+
+
 def test_step_cells_matches_full_step():
     p = _p(12, 11, 13, nu=4e-3, eta=6e-3, dt=1e-3)
     st = mi.noise_state(p, 21, 0.3, 0.3, 0.3)
