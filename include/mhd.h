@@ -60,6 +60,10 @@ typedef struct {
     double nu, eta;          /* viscosity and magnetic diffusivity (>= 0) */
     double dt;               /* time step (> 0) */
     double bext[3];          /* imposed uniform field added to B (zero by default) */
+    double upwind;           /* upwinding of the continuity advection (Section 4): 0 = off
+                                (default), c > 0 adds c |u_a| delta6_a ln rho / (60 h_a) to the
+                                ln rho right-hand side, i.e. for c = 1 each u_a d_a ln rho is
+                                taken with the fifth-order stencil biased against the flow */
 } mhd_params;
 
 /* Forcing record of one step (Section 4, Eqs. forcing, fnorm, feigen):

@@ -36,7 +36,8 @@ class MhdError(RuntimeError):
 class mhd_params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("precision", C.c_int32),
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double), ("cs", C.c_double),
-                ("nu", C.c_double), ("eta", C.c_double), ("dt", C.c_double), ("bext", C.c_double * 3)]
+                ("nu", C.c_double), ("eta", C.c_double), ("dt", C.c_double), ("bext", C.c_double * 3),
+                ("upwind", C.c_double)]
 
 
 class mhd_forcing(C.Structure):
@@ -152,7 +153,7 @@ def _ptr(buf) -> int:
 
 
 def make_params(nx, ny=None, nz=None, *, nu, eta, dt=1e-3, cs=1.0, precision=MHD_FP64,
-                lx=2 * np.pi, ly=2 * np.pi, lz=2 * np.pi, bext=(0.0, 0.0, 0.0)) -> mhd_params:
+                lx=2 * np.pi, ly=2 * np.pi, lz=2 * np.pi, bext=(0.0, 0.0, 0.0), upwind=0.0) -> mhd_params:
     p = mhd_params()
     p.nx = nx
     p.ny = nx if ny is None else ny
@@ -162,13 +163,15 @@ def make_params(nx, ny=None, nz=None, *, nu, eta, dt=1e-3, cs=1.0, precision=MHD
     p.cs, p.nu, p.eta, p.dt = cs, nu, eta, dt
     for a in range(3):
         p.bext[a] = bext[a]
+    p.upwind = upwind
     return p
 
 
 def params_from(rp) -> mhd_params:
     """From any object with the attributes of ``mhd_inputs.RunParams``."""
     return make_params(rp.nx, rp.ny, rp.nz, nu=rp.nu, eta=rp.eta, dt=rp.dt, cs=rp.cs,
-                       precision=rp.precision, lx=rp.lx, ly=rp.ly, lz=rp.lz, bext=rp.bext)
+                       precision=rp.precision, lx=rp.lx, ly=rp.ly, lz=rp.lz, bext=rp.bext,
+                       upwind=getattr(rp, "upwind", 0.0))
 
 
 def forcing_array(recs: Sequence) -> "C.Array":

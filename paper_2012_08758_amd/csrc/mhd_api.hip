@@ -147,6 +147,7 @@ static void fill_coef(const mhd_params &p, Coef<T> &c, DCoef &dc)
         c.bext[a] = (T)p.bext[a];
         dc.bext[a] = p.bext[a];
     }
+    for (int a = 0; a < 3; a++) c.upw[a] = (T)(p.upwind / (60.0 * h[a]));
     for (int s = 0; s < 3; s++) {
         c.bdt[s] = (T)(RK_B[s] * p.dt);
         c.brho[s] = s == 0 ? (T)0 : (T)(RK_B[s] * RK_A[s] / RK_B[s - 1]);
@@ -301,6 +302,7 @@ mhd_status check_params(const mhd_params *p)
         return fail(MHD_E_INVALID, "nu, eta, cs must be finite");
     for (int a = 0; a < 3; a++)
         if (!std::isfinite(p->bext[a])) return fail(MHD_E_INVALID, "bext must be finite");
+    if (!(p->upwind >= 0) || !std::isfinite(p->upwind)) return fail(MHD_E_INVALID, "upwind must be finite and >= 0");
     return MHD_OK;
 }
 
@@ -439,6 +441,9 @@ static hipError_t launch_shape(int kind, const RunDesc<T> *runs, const TileEnt *
     case 0: hipLaunchKernelGGL((k_substep<T, TX, TY, TZ, CZ, 0, true, true, W>), grid, block, 0, st, runs, tiles, step); break;
     case 1: hipLaunchKernelGGL((k_substep<T, TX, TY, TZ, CZ, 1, false, true, W>), grid, block, 0, st, runs, tiles, step); break;
     case 2: hipLaunchKernelGGL((k_substep<T, TX, TY, TZ, CZ, 2, false, true, W>), grid, block, 0, st, runs, tiles, step); break;
+    case 4: hipLaunchKernelGGL((k_substep<T, TX, TY, TZ, CZ, 0, true, true, W, true>), grid, block, 0, st, runs, tiles, step); break;
+    case 5: hipLaunchKernelGGL((k_substep<T, TX, TY, TZ, CZ, 1, false, true, W, true>), grid, block, 0, st, runs, tiles, step); break;
+    case 6: hipLaunchKernelGGL((k_substep<T, TX, TY, TZ, CZ, 2, false, true, W, true>), grid, block, 0, st, runs, tiles, step); break;
     default: hipLaunchKernelGGL((k_substep<T, TX, TY, TZ, CZ, 0, true, false, W>), grid, block, 0, st, runs, tiles, step); break;
     }
     return hipGetLastError();
@@ -454,6 +459,9 @@ static hipError_t launch_pipe(int kind, const RunDesc<T> *runs, const TileEnt *t
     case 0: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 0, true, true, W, FIT>), grid, block, 0, st, runs, tiles, step); break;
     case 1: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 1, false, true, W, FIT>), grid, block, 0, st, runs, tiles, step); break;
     case 2: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 2, false, true, W, FIT>), grid, block, 0, st, runs, tiles, step); break;
+    case 4: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 0, true, true, W, FIT, true>), grid, block, 0, st, runs, tiles, step); break;
+    case 5: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 1, false, true, W, FIT, true>), grid, block, 0, st, runs, tiles, step); break;
+    case 6: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 2, false, true, W, FIT, true>), grid, block, 0, st, runs, tiles, step); break;
     default: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 0, true, false, W, FIT>), grid, block, 0, st, runs, tiles, step); break;
     }
     return hipGetLastError();
@@ -481,6 +489,9 @@ static hipError_t launch_march(int kind, const RunDesc<T> *runs, const TileEnt *
         case 0: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 0, true, true, W>), grid, block, 0, st, runs, tiles, step); break;
         case 1: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 1, false, true, W>), grid, block, 0, st, runs, tiles, step); break;
         case 2: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 2, false, true, W>), grid, block, 0, st, runs, tiles, step); break;
+        case 4: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 0, true, true, W, true>), grid, block, 0, st, runs, tiles, step); break;
+        case 5: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 1, false, true, W, true>), grid, block, 0, st, runs, tiles, step); break;
+        case 6: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 2, false, true, W, true>), grid, block, 0, st, runs, tiles, step); break;
         default: hipLaunchKernelGGL((k_march<T, TX, TY, TZ, 0, true, false, W>), grid, block, 0, st, runs, tiles, step); break;
         }
         return hipGetLastError();
@@ -746,9 +757,13 @@ static mhd_status ctx_stage(mhd_ctx *c, int64_t m, bool diag_only)
     return MHD_OK;
 }
 
+// launch kinds 0-2 are the three substeps, 4-6 the same with upwinding
+static int upwind_kind(const mhd_params &p) { return p.upwind != 0.0 ? 4 : 0; }
+
 template <typename T>
 static mhd_status ctx_step_t(mhd_ctx *c, int64_t nsteps)
 {
+    const int upk = upwind_kind(c->p);
     while (nsteps > 0) {
         const int64_t m = std::min<int64_t>(nsteps, CHUNK);
         if (c->rcount + m > CHUNK) {
@@ -759,10 +774,10 @@ static mhd_status ctx_step_t(mhd_ctx *c, int64_t nsteps)
         if (st != MHD_OK) return st;
         const RunDesc<T> *d = (const RunDesc<T> *)c->d_desc;
         for (int64_t s = 0; s < m; s++) {
-            hipError_t e = launch_substep<T>(c->shape, c->fit, 0, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            hipError_t e = launch_substep<T>(c->shape, c->fit, 0 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = launch_finalize<T>(d, 1, c->nb2, (int)s, c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1, d, c->d_tiles, c->ntiles, (int)s, c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
         }
         c->rcount += m;
@@ -784,6 +799,7 @@ static mhd_status ctx_step_timed_t(mhd_ctx *c, int64_t nsteps, double kms[4], do
     };
     double acc[4] = {0, 0, 0, 0};
     int64_t done = 0;
+    const int upk = upwind_kind(c->p);
     while (nsteps > 0) {
         const int64_t m = std::min<int64_t>(nsteps, CHUNK);
         if (c->rcount + m > CHUNK) {
@@ -800,13 +816,13 @@ static mhd_status ctx_step_timed_t(mhd_ctx *c, int64_t nsteps, double kms[4], do
         for (int64_t s = 0; s < m; s++) {
             hipEvent_t *E = &ev[(size_t)(5 * s)];
             hipError_t e = hipEventRecord(E[0], c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 0, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 0 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[1], c->stream);
             if (e == hipSuccess) e = launch_finalize<T>(d, 1, c->nb2, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[2], c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[3], c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[4], c->stream);
             if (e != hipSuccess) return fail_ev(std::string("launch failed: ") + hipGetErrorString(e));
         }

@@ -48,6 +48,7 @@ struct Coef {
     T bext[3];
     T bdt[3];     // beta_s * dt
     T brho[3];    // beta_s * alpha_s / beta_{s-1} (0 for s = 0)
+    T upw[3];     // upwinding of the continuity advection: c / (60 h_axis)
 };
 
 struct DCoef {      // FP64 inverse spacings and mean field, for the diagnostics
@@ -74,6 +75,25 @@ struct KRegs {
         asm volatile("" : "+s"(cs2), "+s"(nu), "+s"(nu3), "+s"(nu2_3), "+s"(eta));
     }
 };
+
+// with the upwinding coefficients (kernels instantiated with upwinding only)
+template <typename T>
+struct KRegsU : KRegs<T> {
+    T upw[3];
+
+    __device__ __forceinline__ void load(const Coef<T> &c)
+    {
+        KRegs<T>::load(c);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            upw[a] = c.upw[a];
+            asm volatile("" : "+s"(upw[a]));
+        }
+    }
+};
+
+template <typename T, bool UPW>
+using KRegsFor = typename std::conditional<UPW, KRegsU<T>, KRegs<T>>::type;
 
 template <typename T>
 struct RunDesc {
@@ -112,6 +132,13 @@ __device__ __forceinline__ T sd2(const T *s, int st, T ih2)
                   T(W2_3) * (s[3 * st] + s[-3 * st]));
 }
 
+// seven-point sixth difference (h^6 times the sixth derivative, to leading order)
+template <typename T>
+__device__ __forceinline__ T sd6(const T *s, int st)
+{
+    return T(-20) * s[0] + T(15) * (s[st] + s[-st]) + T(-6) * (s[2 * st] + s[-2 * st]) + (s[3 * st] + s[-3 * st]);
+}
+
 // d_a d_b from the (a+b) and (a-b) diagonals
 template <typename T>
 __device__ __forceinline__ T sdm(const T *s, int sa, int sb, T ihm)
@@ -148,6 +175,7 @@ struct Cells {
     double Bd[CZ][3];   // FP64 curl, for the diagnostics
     T old[CZ][NF];      // state of substep s-2 at the cells (filled early by the ring kernel)
     T pend[CZ][3];      // u-first order: d_y u_x, d_z u_x, d_z u_y until u_y / u_z are known
+    T up6[CZ][3];       // upwinding, u-first order: sixth differences of ln rho until u is known
     bool have_old = false;
 };
 
@@ -178,6 +206,13 @@ __device__ __forceinline__ void pin(Cells<T, CZ> &C)
 }
 
 template <typename T, int CZ>
+__device__ __forceinline__ void pin_up6(Cells<T, CZ> &C)
+{
+#pragma unroll
+    for (int c = 0; c < CZ; c++) asm volatile("" : "+v"(C.up6[c][0]), "+v"(C.up6[c][1]), "+v"(C.up6[c][2]));
+}
+
+template <typename T, int CZ>
 __device__ __forceinline__ void pin_pend(Cells<T, CZ> &C, int n)
 {
 #pragma unroll
@@ -193,8 +228,10 @@ __device__ __forceinline__ void pin_pend(Cells<T, CZ> &C, int n)
 // centre value comes from its own field's box: the advection products whose velocity
 // component has not passed yet are held as their derivative (pend) and completed in
 // the later u passes, and -u.grad ln rho is added once u_z has passed.
-template <typename T, int F, int SY, int SZ, int CZ, bool DIAG, bool UFIRST = false>
-__device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&cidx)[CZ], const KRegs<T> &K,
+// UPW: upwinding of the continuity advection, -(u_a d_a ln rho) gains
+// + c |u_a| delta6_a ln rho / (60 h_a) (added once u is known).
+template <typename T, int F, int SY, int SZ, int CZ, bool DIAG, bool UFIRST = false, bool UPW = false, class KR>
+__device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&cidx)[CZ], const KR &K,
                                        const DCoef &dc)
 {
     constexpr int s0 = 1, s1 = SY, s2 = SZ;
@@ -209,6 +246,17 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
                 C.v[c][0] = s[0];
             else
                 C.R[c][0] -= C.v[c][1] * C.g[c][0] + C.v[c][2] * C.g[c][1] + C.v[c][3] * C.g[c][2];
+            if constexpr (UPW) {
+                const T q0 = sd6(s, s0), q1 = sd6(s, s1), q2 = sd6(s, s2);
+                if constexpr (UFIRST) {
+                    C.up6[c][0] = q0;
+                    C.up6[c][1] = q1;
+                    C.up6[c][2] = q2;
+                } else {
+                    C.R[c][0] += K.upw[0] * fabs(C.v[c][1]) * q0 + K.upw[1] * fabs(C.v[c][2]) * q1 +
+                                 K.upw[2] * fabs(C.v[c][3]) * q2;
+                }
+            }
             C.R[c][1] -= K.cs2 * C.g[c][0];
             C.R[c][2] -= K.cs2 * C.g[c][1];
             C.R[c][3] -= K.cs2 * C.g[c][2];
@@ -279,6 +327,9 @@ __device__ __forceinline__ void absorb(Cells<T, CZ> &C, const T *S, const int (&
                     C.R[c][2] -= u[2] * C.pend[c][2];
                     rm -= u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
                     C.R[c][0] -= u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+                    if constexpr (UPW)
+                        C.R[c][0] += K.upw[0] * fabs(u[0]) * C.up6[c][0] + K.upw[1] * fabs(u[1]) * C.up6[c][1] +
+                                     K.upw[2] * fabs(u[2]) * C.up6[c][2];
                 }
             } else {
                 rm -= u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
@@ -431,7 +482,7 @@ __device__ __forceinline__ void finish(Cells<T, CZ> &C, const RunDesc<T> &r, con
     }
 }
 
-template <typename T, int TX, int TY, int TZ, int CZ, int SUB, bool DIAG, bool STORE, int WPE>
+template <typename T, int TX, int TY, int TZ, int CZ, int SUB, bool DIAG, bool STORE, int WPE, bool UPW = false>
 __global__ void __launch_bounds__(TX * TY * (TZ / CZ), WPE)
 k_substep(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
 {
@@ -501,7 +552,7 @@ k_substep(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles
         C.v[c][3] = in[3][gcell[c]];
     }
 
-    KRegs<T> K;
+    KRegsFor<T, UPW> K;
     K.load(r.c);
     const DCoef &dc = r.dc;
     T stage[NL];
@@ -514,42 +565,42 @@ k_substep(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles
     // from hoisting the LDS writes (and their wait on the loads) above the compute.
     stage_load<T, NL, NT, VOL>(stage, in[4], gofs);
     __builtin_amdgcn_sched_barrier(0);
-    absorb<T, 0, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+    absorb<T, 0, SY, SZ, CZ, DIAG, false, UPW>(C, lds[0], cidx, K, dc);
     __builtin_amdgcn_sched_barrier(0);
     stage_store<T, NL, NT, VOL>(lds[1], stage, tid);
     __syncthreads();
     stage_load<T, NL, NT, VOL>(stage, in[5], gofs);
     __builtin_amdgcn_sched_barrier(0);
-    absorb<T, 4, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
+    absorb<T, 4, SY, SZ, CZ, DIAG, false, UPW>(C, lds[1], cidx, K, dc);
     __builtin_amdgcn_sched_barrier(0);
     stage_store<T, NL, NT, VOL>(lds[0], stage, tid);
     __syncthreads();
     stage_load<T, NL, NT, VOL>(stage, in[6], gofs);
     __builtin_amdgcn_sched_barrier(0);
-    absorb<T, 5, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+    absorb<T, 5, SY, SZ, CZ, DIAG, false, UPW>(C, lds[0], cidx, K, dc);
     __builtin_amdgcn_sched_barrier(0);
     stage_store<T, NL, NT, VOL>(lds[1], stage, tid);
     __syncthreads();
     stage_load<T, NL, NT, VOL>(stage, in[1], gofs);
     __builtin_amdgcn_sched_barrier(0);
-    absorb<T, 6, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
+    absorb<T, 6, SY, SZ, CZ, DIAG, false, UPW>(C, lds[1], cidx, K, dc);
     __builtin_amdgcn_sched_barrier(0);
     stage_store<T, NL, NT, VOL>(lds[0], stage, tid);
     __syncthreads();
     if constexpr (STORE) {
         stage_load<T, NL, NT, VOL>(stage, in[2], gofs);
         __builtin_amdgcn_sched_barrier(0);
-        absorb<T, 1, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+        absorb<T, 1, SY, SZ, CZ, DIAG, false, UPW>(C, lds[0], cidx, K, dc);
         __builtin_amdgcn_sched_barrier(0);
         stage_store<T, NL, NT, VOL>(lds[1], stage, tid);
         __syncthreads();
         stage_load<T, NL, NT, VOL>(stage, in[3], gofs);
         __builtin_amdgcn_sched_barrier(0);
-        absorb<T, 2, SY, SZ, CZ, DIAG>(C, lds[1], cidx, K, dc);
+        absorb<T, 2, SY, SZ, CZ, DIAG, false, UPW>(C, lds[1], cidx, K, dc);
         __builtin_amdgcn_sched_barrier(0);
         stage_store<T, NL, NT, VOL>(lds[0], stage, tid);
         __syncthreads();
-        absorb<T, 3, SY, SZ, CZ, DIAG>(C, lds[0], cidx, K, dc);
+        absorb<T, 3, SY, SZ, CZ, DIAG, false, UPW>(C, lds[0], cidx, K, dc);
 
     }
     int gpos[CZ][3];
@@ -720,7 +771,8 @@ constexpr int pipe_lds_bytes()
 //   pass 0: forcing from buffer 2, barrier, field 2 -> 2
 //   passes 1-4: the next field two ahead; pass 5: s-2 state of ln rho, u -> 1;
 //   pass 6: s-2 state of A -> 2; then the update reads them from LDS.
-template <typename T, int TX, int TY, int TZ, int CZ, int SUB, bool DIAG, bool STORE, int WPE, bool FIT>
+template <typename T, int TX, int TY, int TZ, int CZ, int SUB, bool DIAG, bool STORE, int WPE, bool FIT,
+          bool UPW = false>
 __global__ void __launch_bounds__(TX * TY * (TZ / CZ), WPE)
 k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
 {
@@ -804,7 +856,7 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
                              : 0u;
     }
 
-    KRegs<T> K;
+    KRegsFor<T, UPW> K;
     K.load(r.c);
     const DCoef &dc = r.dc;
 
@@ -829,30 +881,33 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     pin(C);
     lds_barrier();  // buffer 2 (forcing slots) is read out
     ring_copy<T, NV, NT, EPL>(in[2], lds[2], voff, wave);
-    absorb<T, 0, SY, SZ, CZ, DIAG, true>(C, lds[0], cidx, K, dc);
+    absorb<T, 0, SY, SZ, CZ, DIAG, true, UPW>(C, lds[0], cidx, K, dc);
+    if constexpr (UPW) pin_up6(C);
 
     ring_barrier<NV>();
     ring_copy<T, NV, NT, EPL>(in[3], lds[0], voff, wave);
-    absorb<T, 1, SY, SZ, CZ, DIAG, true>(C, lds[1], cidx, K, dc);
+    absorb<T, 1, SY, SZ, CZ, DIAG, true, UPW>(C, lds[1], cidx, K, dc);
     pin_pend(C, 2);
+    if constexpr (UPW) pin_up6(C);
 
     ring_barrier<NV>();
     ring_copy<T, NV, NT, EPL>(in[4], lds[1], voff, wave);
-    absorb<T, 2, SY, SZ, CZ, DIAG, true>(C, lds[2], cidx, K, dc);
+    absorb<T, 2, SY, SZ, CZ, DIAG, true, UPW>(C, lds[2], cidx, K, dc);
     pin_pend(C, 3);
+    if constexpr (UPW) pin_up6(C);
 
     ring_barrier<NV>();
     ring_copy<T, NV, NT, EPL>(in[5], lds[2], voff, wave);
-    absorb<T, 3, SY, SZ, CZ, DIAG, true>(C, lds[0], cidx, K, dc);
+    absorb<T, 3, SY, SZ, CZ, DIAG, true, UPW>(C, lds[0], cidx, K, dc);
 
     ring_barrier<NV>();
     ring_copy<T, NV, NT, EPL>(in[6], lds[0], voff, wave);
-    absorb<T, 4, SY, SZ, CZ, DIAG, true>(C, lds[1], cidx, K, dc);
+    absorb<T, 4, SY, SZ, CZ, DIAG, true, UPW>(C, lds[1], cidx, K, dc);
 
     ring_barrier<NV>();
     if constexpr (STORE && SUB != 0)  // buffer 1 (A_x) is read out: the s-2 state of ln rho, u
         Old1::copy(out[0], out[1], out[2], out[3], lds[1], wave, lane, x0s, y0, z0, nx, ny, nz);
-    absorb<T, 5, SY, SZ, CZ, DIAG, true>(C, lds[2], cidx, K, dc);
+    absorb<T, 5, SY, SZ, CZ, DIAG, true, UPW>(C, lds[2], cidx, K, dc);
 
     if constexpr (STORE && SUB != 0) {
         ring_barrier<Old1::NI>();
@@ -861,7 +916,7 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     } else {
         ring_barrier<0>();
     }
-    absorb<T, 6, SY, SZ, CZ, DIAG, true>(C, lds[0], cidx, K, dc);
+    absorb<T, 6, SY, SZ, CZ, DIAG, true, UPW>(C, lds[0], cidx, K, dc);
     if constexpr (STORE && SUB != 0) {
         ring_barrier<0>();
 #pragma unroll
@@ -943,6 +998,18 @@ __device__ __forceinline__ double gd1d(const A &a, double ih)
                  W1_3 * (d(a.template get<P3::x, P3::y, P3::z>()) - d(a.template get<-P3::x, -P3::y, -P3::z>())));
 }
 
+template <typename T, int AX, class A>
+__device__ __forceinline__ T gd6(const A &a)
+{
+    using P1 = Ax<AX, 1>;
+    using P2 = Ax<AX, 2>;
+    using P3 = Ax<AX, 3>;
+    return T(-20) * a.template get<0, 0, 0>() +
+           T(15) * (a.template get<P1::x, P1::y, P1::z>() + a.template get<-P1::x, -P1::y, -P1::z>()) +
+           T(-6) * (a.template get<P2::x, P2::y, P2::z>() + a.template get<-P2::x, -P2::y, -P2::z>()) +
+           (a.template get<P3::x, P3::y, P3::z>() + a.template get<-P3::x, -P3::y, -P3::z>());
+}
+
 // d_a d_b from the (a+b) and (a-b) diagonals
 template <typename T, int AA, int AB, class A>
 __device__ __forceinline__ T gdm(const A &a, T ihm)
@@ -965,8 +1032,15 @@ struct CellM {
     T B[3], J[3];
     T R[NF];
     T du[3][3];   // du[m][a] = d_a u_m, for the advection added at the end
+    T up6[3];     // upwinding: sixth differences of ln rho, added at the end
     double Bd[3];
 };
+
+template <typename T>
+__device__ __forceinline__ void pin_up6(CellM<T> &C)
+{
+    asm volatile("" : "+v"(C.up6[0]), "+v"(C.up6[1]), "+v"(C.up6[2]));
+}
 
 template <typename T>
 __device__ __forceinline__ void pin(CellM<T> &C)
@@ -982,14 +1056,19 @@ __device__ __forceinline__ void pin(CellM<T> &C)
 
 // Fold field F's derivatives at this cell into the accumulators (same terms as
 // absorb, with the advection and induction deferred).
-template <typename T, int F, bool DIAG, class A>
-__device__ __forceinline__ void absorb_m(CellM<T> &C, const A &s, const KRegs<T> &K, const DCoef &dc)
+template <typename T, int F, bool DIAG, bool UPW, class A, class KR>
+__device__ __forceinline__ void absorb_m(CellM<T> &C, const A &s, const KR &K, const DCoef &dc)
 {
     if constexpr (F == 0) {
         C.v[0] = s.template get<0, 0, 0>();
         C.g[0] = gd1<T, 0>(s, K.ih1[0]);
         C.g[1] = gd1<T, 1>(s, K.ih1[1]);
         C.g[2] = gd1<T, 2>(s, K.ih1[2]);
+        if constexpr (UPW) {
+            C.up6[0] = gd6<T, 0>(s);
+            C.up6[1] = gd6<T, 1>(s);
+            C.up6[2] = gd6<T, 2>(s);
+        }
         C.R[1] -= K.cs2 * C.g[0];
         C.R[2] -= K.cs2 * C.g[1];
         C.R[3] -= K.cs2 * C.g[2];
@@ -1047,6 +1126,7 @@ __device__ __forceinline__ void absorb_m(CellM<T> &C, const A &s, const KRegs<T>
         for (int a = 0; a < 3; a++) C.du[m][a] = du[a];
     }
     pin(C);
+    if constexpr (UPW) pin_up6(C);
 }
 
 // Planes [za, za + n) of one field into its ring (slot of plane z: (z - zbase) mod P),
@@ -1100,7 +1180,7 @@ struct MarchCfg {
     static constexpr bool FITS = LDS_BYTES <= 160 * 1024;
 };
 
-template <typename T, int TX, int TY, int TZ, int SUB, bool DIAG, bool STORE, int WPE>
+template <typename T, int TX, int TY, int TZ, int SUB, bool DIAG, bool STORE, int WPE, bool UPW = false>
 __global__ void __launch_bounds__(TX * TY * TZ, WPE)
 k_march(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
 {
@@ -1145,7 +1225,7 @@ k_march(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, 
     const int gxc = x0s + lx >= nx ? x0s + lx - nx : x0s + lx, gyc = y0 + ly;
     const int xyoff = (ly + 3) * SY + (lx + 4);
 
-    KRegs<T> K;
+    KRegsFor<T, UPW> K;
     K.load(r.c);
     const DCoef &dc = r.dc;
     const G<T> *fblk = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
@@ -1209,33 +1289,33 @@ k_march(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, 
             Old::copy(out[0], out[1], out[2], out[3], old_area, wave, lane, x0s, y0, z0, nx, ny, nz);
             Old3::copy(out[4], out[5], out[6], out[6], old_area + 4 * NT, wave, lane, x0s, y0, z0, nx, ny, nz);
         }
-        absorb_m<T, 0, DIAG>(C, acc_for(0), K, dc);
+        absorb_m<T, 0, DIAG, UPW>(C, acc_for(0), K, dc);
 
         // pass 1: A_x; ln rho's next planes, this slab's forcing slots
         wait_bar(std::integral_constant<int, 5 * ND + ES + NO>{});
         planes(0, z0 + TZ + 3, TZc{});
         if constexpr (STORE) Frc::copy(fblk, frc, lane, x0s, y0, z0, nx, ny, nz);
-        absorb_m<T, 4, DIAG>(C, acc_for(1), K, dc);
+        absorb_m<T, 4, DIAG, UPW>(C, acc_for(1), K, dc);
 
         wait_bar(std::integral_constant<int, 5 * ND + ES + NO + NFC>{});
         planes(1, z0 + TZ + 3, TZc{});
-        absorb_m<T, 5, DIAG>(C, acc_for(2), K, dc);
+        absorb_m<T, 5, DIAG, UPW>(C, acc_for(2), K, dc);
 
         wait_bar(std::integral_constant<int, 5 * ND + ES + NO + NFC>{});
         planes(2, z0 + TZ + 3, TZc{});
-        absorb_m<T, 6, DIAG>(C, acc_for(3), K, dc);
+        absorb_m<T, 6, DIAG, UPW>(C, acc_for(3), K, dc);
 
         wait_bar(std::integral_constant<int, 5 * ND + ES + NO + NFC>{});
         planes(3, z0 + TZ + 3, TZc{});
-        absorb_m<T, 1, DIAG>(C, acc_for(4), K, dc);
+        absorb_m<T, 1, DIAG, UPW>(C, acc_for(4), K, dc);
 
         wait_bar(std::integral_constant<int, 5 * ND + ES + NO + NFC>{});
         planes(4, z0 + TZ + 3, TZc{});
-        absorb_m<T, 2, DIAG>(C, acc_for(5), K, dc);
+        absorb_m<T, 2, DIAG, UPW>(C, acc_for(5), K, dc);
 
         wait_bar(std::integral_constant<int, 5 * ND + NO + NFC>{});
         planes(5, z0 + TZ + 3, TZc{});
-        absorb_m<T, 3, DIAG>(C, acc_for(6), K, dc);
+        absorb_m<T, 3, DIAG, UPW>(C, acc_for(6), K, dc);
 
         // the end of the slab: deferred terms, forcing, RK update
         wait_bar(std::integral_constant<int, 5 * ND>{});
@@ -1243,6 +1323,9 @@ k_march(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, 
 #pragma unroll
         for (int m = 0; m < 3; m++) C.R[1 + m] -= u[0] * C.du[m][0] + u[1] * C.du[m][1] + u[2] * C.du[m][2];
         C.R[0] -= u[0] * C.g[0] + u[1] * C.g[1] + u[2] * C.g[2];
+        if constexpr (UPW)
+            C.R[0] += K.upw[0] * fabs(u[0]) * C.up6[0] + K.upw[1] * fabs(u[1]) * C.up6[1] +
+                      K.upw[2] * fabs(u[2]) * C.up6[2];
         C.R[4] += u[1] * C.B[2] - u[2] * C.B[1];
         C.R[5] += u[2] * C.B[0] - u[0] * C.B[2];
         C.R[6] += u[0] * C.B[1] - u[1] * C.B[0];

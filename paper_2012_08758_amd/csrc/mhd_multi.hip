@@ -28,6 +28,7 @@ struct Group {
     int prec = 8;
     int shape = 0;
     bool fit = false;
+    int upk = 0;               // 4 when the group's runs use upwinding (launch kinds 4-6)
     std::vector<mhd_ctx *> members;
     int ntiles = 0;
     int max_nb2 = 0;
@@ -100,9 +101,10 @@ struct MultiRunner {
         groups.clear();
         if (!stage_evt && hipEventCreateWithFlags(&stage_evt, hipEventDisableTiming) != hipSuccess)
             return fail(MHD_E_DEVICE, "hipEventCreate failed");
-        std::map<std::tuple<int, int, bool>, size_t> index;
+        std::map<std::tuple<int, int, bool, int>, size_t> index;
         for (mhd_ctx *c : runs) {
-            auto key = std::make_tuple(c->p.precision, c->shape, c->fit);
+            const int upk = c->p.upwind != 0.0 ? 4 : 0;
+            auto key = std::make_tuple(c->p.precision, c->shape, c->fit, upk);
             auto it = index.find(key);
             if (it == index.end()) {
                 index[key] = groups.size();
@@ -110,6 +112,7 @@ struct MultiRunner {
                 g.prec = c->p.precision;
                 g.shape = c->shape;
                 g.fit = c->fit;
+                g.upk = upk;
                 groups.push_back(g);
                 it = index.find(key);
             }
@@ -137,10 +140,10 @@ struct MultiRunner {
     {
         const RunDesc<T> *d = (const RunDesc<T> *)g.d_descs;
         const int nr = (int)g.members.size();
-        hipError_t e = launch_substep<T>(g.shape, g.fit, 0, d, g.d_tiles, g.ntiles, s, stream);
+        hipError_t e = launch_substep<T>(g.shape, g.fit, 0 + g.upk, d, g.d_tiles, g.ntiles, s, stream);
         if (e == hipSuccess) e = launch_finalize<T>(d, nr, g.max_nb2, s, stream);
-        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 1, d, g.d_tiles, g.ntiles, s, stream);
-        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 2, d, g.d_tiles, g.ntiles, s, stream);
+        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 1 + g.upk, d, g.d_tiles, g.ntiles, s, stream);
+        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 2 + g.upk, d, g.d_tiles, g.ntiles, s, stream);
         return e;
     }
 

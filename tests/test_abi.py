@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     mhd = _mhd()
-    assert C.sizeof(mhd.mhd_params) == 4 * 4 + 10 * 8
+    assert C.sizeof(mhd.mhd_params) == 4 * 4 + 11 * 8
     assert C.sizeof(mhd.mhd_forcing) == 4 * 4 + 6 * 8
     assert C.sizeof(mhd.mhd_diag) == 8 + 11 * 8
 
@@ -47,6 +47,7 @@ def test_struct_layouts_match_header():
 @pytest.mark.parametrize("bad", [
     dict(nx=7), dict(ny=4), dict(precision=2), dict(dt=0.0), dict(dt=-1e-3), dict(nu=-1.0),
     dict(eta=float("nan")), dict(lx=0.0), dict(nx=70000), dict(bext=(0.0, float("inf"), 0.0)),
+    dict(upwind=-1.0), dict(upwind=float("nan")),
 ])
 def test_invalid_parameters_are_rejected_before_device_work(bad):
     mhd = _mhd()

@@ -167,6 +167,26 @@ def test_march_shapes_several_slabs(mhd, shape, prec):
         assert abs(rec[k] - ref[k]) <= 1e-12 * max(abs(ref[k]), 1e-300), (k, rec[k], ref[k])
 
 
+@pytest.mark.parametrize("prec", [8, 4])
+@pytest.mark.parametrize("shape", [0, 9, 10, 12, 13])
+def test_upwinding_parity(mhd, shape, prec):
+    """Upwinding of the continuity advection on (staged, ring CZ=2, ring, marching)
+    kernels: two steps against the oracle, with rough ln rho and u so that the
+    sixth-difference correction is far from negligible."""
+    rp = mi.RunParams(64, 48, 40, nu=3e-3, eta=2e-3, dt=1e-3, precision=prec, upwind=1.0)
+    st = mi.noise_state(rp, 90 + shape, 0.2, 0.3, 0.2, dtype=_dtype(prec))
+    recs = mi.forcing_schedule(5, 2, 3.0, 0.05, 0.5)
+    got, _ = gpu_run(mhd, rp, st, recs, per_step=True, shape=shape)
+    want, scales = oracle_per_step(st, rp, recs)
+    for n in range(2):
+        check_step(got[n], want[n], scales[n], rp, f"upwind shape {shape} fp{8 * prec} step {n + 1}")
+    # and the term is really there: the step without it differs well beyond the bar
+    q = mi.RunParams(64, 48, 40, nu=3e-3, eta=2e-3, dt=1e-3, precision=prec)
+    plain, _ = oracle.step(st.astype(np.float64), q, recs[:1])
+    e, _ = oracle.tolerance_error(plain, want[0], scales[0], rp.dt)
+    assert e[0] > 100 * TOL[prec], e
+
+
 @pytest.mark.parametrize("n", [8, 9, 33])
 def test_small_and_odd_grids(mhd, n):
     """Grids smaller than a tile (the halo wraps more than once) and odd sizes."""
@@ -322,10 +342,11 @@ def test_borrowed_torch_buffers(mhd):
 
 
 def _batch_specs():
+    # one run per precision with upwinding: those go to launches of their own
     return [mi.RunParams(16, 16, 16, nu=5e-3, eta=5e-3, precision=8),
-            mi.RunParams(24, 20, 16, nu=2e-3, eta=2e-3, precision=8),
+            mi.RunParams(24, 20, 16, nu=2e-3, eta=2e-3, precision=8, upwind=1.0),
             mi.RunParams(32, 32, 32, nu=1e-3, eta=1e-3, precision=4),
-            mi.RunParams(20, 20, 24, nu=4e-4, eta=4e-4, precision=4)]
+            mi.RunParams(20, 20, 24, nu=4e-4, eta=4e-4, precision=4, upwind=0.5)]
 
 
 @pytest.mark.parametrize("use_graph", [True, False])
