@@ -1,13 +1,15 @@
 // Device-side data structures and kernels of the MHD solver (gfx950).
 //
 // One launch = one RK3 substep of every run in a tile list.  Each work-group owns a
-// TX x TY x TZ box of cells of one run.  The seven fields pass through a
-// double-buffered LDS tile one at a time (box + 3-cell halo, periodic indices
-// wrapped while staging); while field f is differentiated out of one buffer, field
-// f+1 streams from HBM into the other.  Every right-hand-side term is folded into
-// per-cell accumulators as soon as the field it needs has passed, so registers
-// hold ~23 values per cell instead of ~60 derivatives.  The RK3 update is fused:
-// the output of substep s overwrites, cell by cell, the buffer holding substep s-2.
+// TX x TY x TZ box of cells of one run (or, in the marching kernel, a TX x TY column
+// of one z-segment).  The seven fields pass through LDS one at a time (box + 3-cell
+// halo, periodic indices wrapped while staging), the next fields streaming in while
+// the current one is differentiated: through registers in k_substep, by direct-to-
+// LDS loads into a ring of three boxes in k_pipe, into per-field plane rings in
+// k_march.  Every right-hand-side term is folded into per-cell accumulators as soon
+// as the fields it needs have passed, so registers hold ~23 values per cell instead
+// of ~60 derivatives.  The RK3 update is fused: the output of substep s overwrites,
+// cell by cell, the buffer holding substep s-2.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -1,0 +1,82 @@
+"""Low-Rm sanity check of the dynamo growth rate against the paper's Tables 1 and 2.
+
+Runs their cheapest rows (Section 5.1): N = 64, nu = eta = 5e-3 (Pm = 1), forcing at
+k_f = 5 with f0 = 0.08, helical (sigma = 1) and non-helical (sigma = 0), upwinding of
+the continuity advection on, from the weak random seed field, and fits
+B_rms ~ exp(lambda t) over the kinematic stage.  The paper lists lambda = 1.73e-2 and
+-1.35e-2 for these rows at Re_M = u_rms / (eta k_f) = 3.6; its forcing draws are random
+and its fit windows were set by hand, so only loose agreement is expected.  Besides
+the printed f0 = 0.08 it runs a weaker forcing (0.03), which reaches the paper's Re_M
+with the forcing as printed.  Only the solver's own API is used.
+
+    python -m paper_2012_08758_amd.growth_check [--tmax 500] [--dt 2e-3] [--seed 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+PAPER_LAMBDA = {1.0: 1.73e-2, 0.0: -1.35e-2}  # Tables 1 and 2, N = 64, eta = 5e-3
+
+
+def run(mhd, sigma: float, tmax: float, dt: float, seed: int, n: int = 64, eta: float = 5e-3, f0: float = 0.08):
+    p = mhd.make_params(n, nu=eta, eta=eta, dt=dt, precision=mhd.MHD_FP64, upwind=1.0)
+    h = mhd.mhd_create(p)
+    t0 = time.perf_counter()
+    try:
+        mhd.mhd_init_seed(h, seed, 1e-5)
+        mhd.mhd_set_forcing_random(h, 5.0, f0, sigma, seed)
+        nsteps = int(round(tmax / dt))
+        recs = []
+        done = 0
+        while done < nsteps:
+            k = min(5000, nsteps - done)
+            mhd.mhd_step(h, k)
+            done += k
+            d = mhd.mhd_get_diag(h)
+            recs.extend(d[::10])  # every tenth step is plenty for the fit
+            mhd.mhd_clear_diag(h)
+            if d and not math.isfinite(d[-1]["brms"]):
+                break
+    finally:
+        mhd.mhd_destroy(h)
+    wall = time.perf_counter() - t0
+    t = np.array([r["t"] for r in recs])
+    b = np.array([r["brms"] for r in recs])
+    u = np.array([r["urms"] for r in recs])
+    # kinematic stage: after the first fifth of the run (turbulence and the seed
+    # field's transient), before B_rms reaches a tenth of u_rms (saturation onset)
+    lo = int(np.searchsorted(t, tmax / 5.0))
+    sat = np.nonzero(b[lo:] > 0.1 * u[lo:])[0]
+    hi = lo + int(sat[0]) if len(sat) and sat[0] > 10 else len(t)
+    lam = mhd.mhd_growth_rate(recs, lo, hi)
+    urms = float(u[lo:hi].mean())
+    return dict(sigma=sigma, f0=f0, lam=lam, paper=PAPER_LAMBDA.get(sigma),
+                fit_window=[float(t[lo]), float(t[hi - 1])], urms=urms, rm=urms / (eta * 5.0),
+                paper_rm=3.6, brms_end=float(b[-1]), steps=nsteps, wall_s=wall)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--tmax", type=float, default=500.0)
+    ap.add_argument("--dt", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--f0", type=float, nargs="+", default=[0.08, 0.03],
+                    help="forcing amplitudes to run (the paper's 0.08, and others to match its Re_M)")
+    args = ap.parse_args(argv)
+    import paper_2012_08758_amd as mhd
+    out = [run(mhd, s, args.tmax, args.dt, args.seed, f0=f0) for f0 in args.f0 for s in (1.0, 0.0)]
+    for r in out:
+        print(f"f0={r['f0']} sigma={r['sigma']:.0f}: lambda = {r['lam']:+.3e} (paper {r['paper']:+.2e}) over t in "
+              f"[{r['fit_window'][0]:.0f}, {r['fit_window'][1]:.0f}], u_rms {r['urms']:.3f} (Re_M {r['rm']:.1f}, "
+              f"paper 3.6), {r['steps']} steps in {r['wall_s']:.1f} s", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
