@@ -4,6 +4,9 @@ TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  The solver package
 never imports it, and it imports nothing from the solver.
 
+The magnetic power spectrum (``magnetic_spectrum``) is the discrete curl followed by
+a library FFT over the full grid and a shell sum, written from its definition.
+
 Two independent implementations live here:
   * ``mhd_oracle.c`` (built into ``liboracle.so``): plain C loops with periodic
     wrap, OpenMP over z-planes, used at every size;
@@ -205,6 +208,58 @@ def growth_rate(t, brms, i0=0, i1=None) -> float:
     y = np.log(np.asarray(brms, dtype=np.float64)[i0:i1])
     tc = t - t.mean()
     return float(np.sum(tc * (y - y.mean())) / np.sum(tc * tc))
+
+
+def magnetic_spectrum(state, p):
+    """Shell spectrum E_B(k) of the discrete magnetic field (Section 6.2 power spectra).
+
+    Follows the definition: B = curl A with the sixth-order first derivative (plus
+    B_ext), its discrete Fourier transform B_hat(k) = sum_x B(x) exp(-i k.x) (a
+    library FFT over the full grid), and the energy of every wavevector summed into
+    the shell s with s - 1/2 <= |k|/dk < s + 1/2, dk = 2 pi / max(L).  Normalised
+    so that sum_s E_B(s) dk = (1/2) int |B|^2 dV (volume integral, mu0 = 1):
+    E_B(s) = V / (2 dk Ncell^2) * sum_{k in s} |B_hat(k)|^2.  The shell index is
+    computed from m_a * (max(L) / L_a) in the order x, y, z, squared, summed, square
+    root, + 1/2, floor, all in FP64.  Returns (E, dk).
+    """
+    st = _state64(state, p)
+    h = (p.lx / p.nx, p.ly / p.ny, p.lz / p.nz)
+    A = st[4:7]
+    bext = tuple(getattr(p, "bext", (0.0, 0.0, 0.0)))
+    B = np.empty_like(A)
+    for c, (a, b) in enumerate(((1, 2), (2, 0), (0, 1))):
+        # B_c = d_a A_b - d_b A_a for the cyclic triple (c, a, b)
+        B[c] = deriv(A[b], h, 1, a) - deriv(A[a], h, 1, b) + bext[c]
+    lmax = max(p.lx, p.ly, p.lz)
+    dk = 2.0 * np.pi / lmax
+    r = (lmax / p.lx, lmax / p.ly, lmax / p.lz)
+    mz, my, mx = np.meshgrid(np.fft.fftfreq(p.nz, 1.0 / p.nz), np.fft.fftfreq(p.ny, 1.0 / p.ny),
+                             np.fft.fftfreq(p.nx, 1.0 / p.nx), indexing="ij")
+    q = (mx * r[0]) ** 2 + (my * r[1]) ** 2
+    q = q + (mz * r[2]) ** 2
+    shell = np.floor(np.sqrt(q) + 0.5).astype(np.int64)
+    nshell = spectrum_nshell(p)
+    power = np.zeros(shell.shape)
+    for c in range(3):
+        F = np.fft.fftn(B[c])
+        power += F.real ** 2 + F.imag ** 2
+    E = np.bincount(shell.ravel(), weights=power.ravel(), minlength=nshell)
+    vol = p.lx * p.ly * p.lz
+    ncell = float(p.nx * p.ny * p.nz)
+    return E * (vol / (2.0 * dk * ncell * ncell)), dk
+
+
+def spectrum_nshell(p) -> int:
+    """Number of shells: the shell of the corner wavevector (n_a // 2 per axis), plus one."""
+    lmax = max(p.lx, p.ly, p.lz)
+    q = ((p.nx // 2) * (lmax / p.lx)) ** 2 + ((p.ny // 2) * (lmax / p.ly)) ** 2
+    q = q + ((p.nz // 2) * (lmax / p.lz)) ** 2
+    return int(np.floor(np.sqrt(q) + 0.5)) + 1
+
+
+def spectral_growth_rate(t, ek, i0=0, i1=None) -> float:
+    """Growth rate lambda_k of one spectral channel, E_B,k ~ exp(2 lambda_k t) (Section 5.1)."""
+    return 0.5 * growth_rate(t, ek, i0, i1)
 
 
 def tolerance_error(gpu, ora, tscale, dt):

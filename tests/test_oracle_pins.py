@@ -534,3 +534,117 @@ def test_growth_rate_fit_is_exact_on_an_exponential():
     lam = 0.0173
     assert abs(oracle.growth_rate(t, 1e-5 * np.exp(lam * t)) - lam) < 1e-10
     assert abs(oracle.growth_rate(t, 3.0 * np.exp(-0.8 * t), 100, 200) + 0.8) < 1e-10
+
+
+# ------------------------------------------------------------------ magnetic spectrum
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_spectrum_of_a_beltrami_field_is_one_shell(axis):
+    # A = (sin kz, cos kz, 0)/k and its cyclic permutations: the discrete B is a
+    # single Fourier shell |k| with |B|^2 = (k_eff/k)^2 everywhere, so the whole energy
+    # (1/2) V (k_eff/k)^2 sits in shell k (dk = 1 for L = 2 pi).
+    p = _p(32, 24, 20)
+    X = _coords(p)
+    k = 3
+    h = (p.lx / p.nx, p.ly / p.ny, p.lz / p.nz)[axis]
+    st = np.zeros((7,) + X[0].shape)
+    a, b = (axis + 1) % 3, (axis + 2) % 3
+    st[4 + a] = np.sin(k * X[axis]) / k
+    st[4 + b] = np.cos(k * X[axis]) / k
+    E, dk = oracle.magnetic_spectrum(st, p)
+    assert dk == 1.0
+    assert len(E) == oracle.spectrum_nshell(p) == int(math.floor(math.sqrt(16 ** 2 + 12 ** 2 + 10 ** 2) + 0.5)) + 1
+    want = 0.5 * TWO_PI ** 3 * (keff(k, h) / k) ** 2
+    assert abs(E[k] - want) <= 1e-13 * want
+    assert np.max(np.abs(np.delete(E, k))) <= 1e-14 * want
+
+
+@pytest.mark.parametrize("kvec,shell", [((1, 2, 2), 3), ((3, 0, -4), 5), ((-2, 3, 6), 7)])
+def test_spectrum_of_an_oblique_mode(kvec, shell):
+    # A = a cos(k.x + phi): B = -sin(k.x + phi) (kappa x a) with kappa_a the sixth-order
+    # modified wavenumber of axis a, so <|B|^2> = |kappa x a|^2 / 2 and the shell |k|
+    # holds V |kappa x a|^2 / 4.
+    p = _p(16, 12, 14)
+    X = _coords(p)
+    a = np.array([0.3, -0.2, 0.5])
+    th = kvec[0] * X[0] + kvec[1] * X[1] + kvec[2] * X[2] + 0.7
+    st = np.zeros((7,) + X[0].shape)
+    for c in range(3):
+        st[4 + c] = a[c] * np.cos(th)
+    hs = (p.lx / p.nx, p.ly / p.ny, p.lz / p.nz)
+    kap = np.array([math.copysign(keff(abs(kk), hh), kk) for kk, hh in zip(kvec, hs)])
+    want = TWO_PI ** 3 * float(np.sum(np.cross(kap, a) ** 2)) / 4
+    E, _ = oracle.magnetic_spectrum(st, p)
+    assert abs(E[shell] - want) <= 1e-13 * want
+    assert np.max(np.abs(np.delete(E, shell))) <= 1e-14 * want
+
+
+def test_spectrum_matches_a_direct_fourier_sum_on_a_small_box():
+    # Brute force from the definition on a non-cubic box: B from the np.roll stencils,
+    # B_hat(k) = sum_x B(x) exp(-i k.x) summed directly with physical k and x, every
+    # wavevector placed by |k| / dk rounded to the nearest shell, dk = 2 pi / max(L).
+    p = _p(8, 6, 10, lx=TWO_PI, ly=3.1, lz=7.3, bext=(0.05, -0.1, 0.02))
+    st = mi.noise_state(p, 5, 0.0, 0.0, 0.4)
+    h = (p.lx / p.nx, p.ly / p.ny, p.lz / p.nz)
+    A = st[4:7]
+    B = np.stack([numpy_ref.d1(A[2], 1, h[1]) - numpy_ref.d1(A[1], 2, h[2]),
+                  numpy_ref.d1(A[0], 2, h[2]) - numpy_ref.d1(A[2], 0, h[0]),
+                  numpy_ref.d1(A[1], 0, h[0]) - numpy_ref.d1(A[0], 1, h[1])])
+    B += np.array(p.bext)[:, None, None, None]
+    xs = [np.arange(n) * L / n for n, L in ((p.nx, p.lx), (p.ny, p.ly), (p.nz, p.lz))]
+    dk = TWO_PI / max(p.lx, p.ly, p.lz)
+    vol = p.lx * p.ly * p.lz
+    E = {}
+    margin = 1.0
+    for mz in range(-(p.nz // 2), (p.nz + 1) // 2):
+        for my in range(-(p.ny // 2), (p.ny + 1) // 2):
+            for mx in range(-(p.nx // 2), (p.nx + 1) // 2):
+                kp = (TWO_PI * mx / p.lx, TWO_PI * my / p.ly, TWO_PI * mz / p.lz)
+                ph = np.exp(-1j * (kp[2] * xs[2][:, None, None] + kp[1] * xs[1][None, :, None]
+                                   + kp[0] * xs[0][None, None, :]))
+                pw = sum(abs(np.sum(B[c] * ph)) ** 2 for c in range(3))
+                s = math.sqrt(kp[0] ** 2 + kp[1] ** 2 + kp[2] ** 2) / dk
+                margin = min(margin, abs(s - math.floor(s) - 0.5))
+                E[int(math.floor(s + 0.5))] = E.get(int(math.floor(s + 0.5)), 0.0) + pw
+    assert margin > 1e-6  # no wavevector near a shell boundary: the rounding is unambiguous
+    n2 = float(p.ncell) ** 2
+    got, dk_o = oracle.magnetic_spectrum(st, p)
+    assert abs(dk_o - dk) < 1e-15
+    want = np.zeros(len(got))
+    for s, v in E.items():
+        want[s] = v * vol / (2 * dk * n2)
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.sum(want)
+
+
+def test_spectrum_sums_to_the_magnetic_energy_with_a_mean_field():
+    # Parseval: sum_s E_B(s) dk = (1/2) int |B|^2 dV = V E_M, and the uniform field
+    # B_ext alone fills shell 0 with (1/2) V |B_ext|^2 / dk.
+    p = _p(12, 10, 16, lx=5.0, ly=TWO_PI, lz=4.0, bext=(0.1, -0.2, 0.05))
+    st = mi.noise_state(p, 9, 0.2, 0.2, 0.3)
+    E, dk = oracle.magnetic_spectrum(st, p)
+    vol = p.lx * p.ly * p.lz
+    em = oracle.diag(st, p)["em"]
+    assert abs(np.sum(E) * dk - vol * em) <= 1e-13 * vol * em
+    assert abs(E[0] * dk - 0.5 * vol * (0.1 ** 2 + 0.2 ** 2 + 0.05 ** 2)) <= 1e-13 * vol * em
+
+
+def test_channel_growth_rate_of_a_decaying_beltrami_field_equals_the_rms_rate():
+    # With u = 0 and a Beltrami A the discrete system is linear: each step multiplies A
+    # by G(-eta k2^2 dt), the RK3 polynomial.  The channel E_B(k) ~ exp(2 lambda_k t)
+    # and B_rms ~ exp(lambda t) then give the same lambda = ln|G| / dt.
+    p = _p(16, eta=2e-2, dt=5e-3)
+    X = _coords(p)
+    k = 2
+    st = np.zeros((7,) + X[0].shape)
+    st[4] = np.sin(k * X[2]) / k
+    st[5] = np.cos(k * X[2]) / k
+    ts, ek, br = [], [], []
+    for n in range(6):
+        ts.append(n * p.dt)
+        ek.append(oracle.magnetic_spectrum(st, p)[0][k])
+        br.append(oracle.diag(st, p)["brms"])
+        st, _ = oracle.step(st, p, [NOFORCE])
+    h = TWO_PI / 16
+    lam = math.log(abs(rk3_poly(-p.eta * k2eff(k, h) ** 2 * p.dt))) / p.dt
+    assert abs(oracle.spectral_growth_rate(ts, ek) - lam) < 1e-10
+    assert abs(oracle.growth_rate(ts, br) - lam) < 1e-10
