@@ -126,6 +126,26 @@ def fp32_vs_fp64(mhd, h64, h32, n):
     return out
 
 
+def spectrum_timing(mhd, h, n, prec, reps=5):
+    """Magnetic power spectrum of a live n^3 run: wall time per synchronous call (the
+    first call, which allocates the workspace, is not timed) against the bytes its pass
+    structure moves: the x pass reads the three A components and writes their half
+    spectra (U = 3 (n/2+1) n^2 complex FP64 values), the y and z passes read and write U
+    each, the binning pass reads U."""
+    E, dk = mhd.mhd_spectrum(h)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        E, dk = mhd.mhd_spectrum(h)
+        ts.append((time.perf_counter() - t0) * 1e3)
+    u = 3.0 * (n // 2 + 1) * n * n * 16.0
+    nbytes = 3.0 * n ** 3 * prec + 6.0 * u
+    ms = float(np.mean(ts))
+    return dict(ms_per_call=ms, min_ms=float(np.min(ts)), bytes_per_call=nbytes,
+                gbs=nbytes / (ms * 1e-3) / 1e9, roofline_frac=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                nshell=len(E), dk=dk, em_from_spectrum=float(np.sum(E) * dk / (2 * np.pi) ** 3))
+
+
 def shape_sweep(mhd, n, steps=3):
     out = {}
     for prec in (mhd.MHD_FP64, mhd.MHD_FP32):
@@ -310,6 +330,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-spectrum", action="store_true")
     ap.add_argument("--serve-runs", type=int, default=40)
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--cpu-nz", type=int, default=64)
@@ -347,6 +368,7 @@ def main():
     log(f"[bench] FP64 {r64['cell_substeps_per_s']:.3e} cell-substeps/s, {r64['ms_per_step']:.2f} ms/step")
     r32 = None
     fp32_err = None
+    spec = None
     if not args.no_fp32:
         log(f"[bench] {args.n}^3 FP32")
         r32 = single_run(mhd, args.n, mhd.MHD_FP32, args.warmup, args.steps, keep=True)
@@ -355,6 +377,12 @@ def main():
             fp32_err = fp32_vs_fp64(mhd, r64["handle"], r32["handle"], args.n)
             log("[bench] FP32 vs FP64 after %d steps: " % r32["steps_done"]
                 + " ".join(f"{k}:{v:.1e}" for k, v in fp32_err.items()))
+            if not args.no_spectrum:
+                spec = {}
+                for name, h, prec in (("fp64", r64["handle"], 8), ("fp32", r32["handle"], 4)):
+                    spec[name] = spectrum_timing(mhd, h, args.n, prec)
+                    log(f"[bench] spectrum {name}: {spec[name]['ms_per_call']:.2f} ms/call, "
+                        f"{spec[name]['gbs']:.0f} GB/s of its pass structure")
         finally:
             mhd.mhd_destroy(r64["handle"])
             mhd.mhd_destroy(r32["handle"])
@@ -421,6 +449,7 @@ def main():
             "tile": r32["tile"]},
         "ensemble": ens,
         "serving": srv,
+        "spectrum": spec,
     }
     if sweep is not None:
         out["shape_sweep"] = sweep

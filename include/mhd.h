@@ -167,6 +167,32 @@ mhd_status mhd_field_ptr(mhd_ctx *ctx, int field, void **dptr);
 mhd_status mhd_growth_rate(const mhd_diag *d, int64_t n, int64_t i0, int64_t i1,
                            double *lambda);
 
+/* Magnetic power spectrum of the current state (Section 6.2).  B = curl A with the
+ * sixth-order first derivative (plus b_ext); with B_hat(k) = sum_x B(x) exp(-i k.x),
+ * shell s (s = 0 .. nshell-1) collects the wavevectors with s - 1/2 <= |k|/dk < s + 1/2,
+ * dk = 2 pi / max(lx, ly, lz), and out[s] = V / (2 dk Ncell^2) * sum_{k in s} |B_hat(k)|^2,
+ * so that sum_s out[s] dk = (1/2) int |B|^2 dV (V = lx ly lz, mu0 = 1).  Computed on the
+ * run's stream in FP64 at either precision: an FFT of the three A components, the curl
+ * applied as its Fourier symbol i kappa(k) x (kappa_a the modified wavenumber of the
+ * first-derivative stencil), a deterministic shell sum.  Every grid side must be a product
+ * of 2, 3, 5 and 7 and at most 4096 (else MHD_E_UNSUPPORTED).  Writes min(cap, nshell)
+ * values to the host array out, the shell count to *nshell and the shell width to *dk
+ * (either may be NULL); cap = 0 only queries nshell and dk (no device work).
+ * Synchronises.  The first computing call allocates a device workspace of about
+ * 48 (nx/2+1) ny nz bytes (mhd_spectrum_shells reports it), kept until mhd_destroy;
+ * MHD_E_OOM if it does not fit. */
+mhd_status mhd_spectrum(mhd_ctx *ctx, double *out, int32_t cap, int32_t *nshell, double *dk);
+
+/* Shell count, shell width and spectrum workspace bytes for runs of this size
+ * (host-only).  MHD_E_UNSUPPORTED (outputs still written) if a side is not a product of
+ * 2, 3, 5 and 7 at most 4096. */
+mhd_status mhd_spectrum_shells(const mhd_params *p, int32_t *nshell, double *dk, size_t *workspace_bytes);
+
+/* Growth rate of one spectral channel from samples (t_i, E_i), i < n: half the
+ * least-squares slope of ln E against t (Section 5.1: E_B,k ~ exp(2 lambda_k t), so that
+ * lambda_k and the B_rms rate agree).  Host-only, FP64.  Needs n >= 2, E_i > 0. */
+mhd_status mhd_channel_growth_rate(const double *t, const double *e, int64_t n, double *lambda);
+
 /* Thread-local message of the last failure ("" if none). */
 const char *mhd_last_error(void);
 

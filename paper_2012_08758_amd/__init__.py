@@ -89,6 +89,12 @@ _SIGS = {
     "mhd_field_ptr": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     "mhd_growth_rate": (C.c_int, [C.POINTER(mhd_diag), C.c_int64, C.c_int64, C.c_int64,
                                   C.POINTER(C.c_double)]),
+    "mhd_spectrum": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double)]),
+    "mhd_spectrum_shells": (C.c_int, [C.POINTER(mhd_params), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_size_t)]),
+    "mhd_channel_growth_rate": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int64,
+                                          C.POINTER(C.c_double)]),
     "mhd_last_error": (C.c_char_p, []),
     "mhd_forcing_draw": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_int64,
                                    C.POINTER(mhd_forcing)]),
@@ -302,6 +308,34 @@ def mhd_growth_rate(records: Sequence[dict], i0: int = 0, i1: Optional[int] = No
     return lam.value
 
 
+def mhd_spectrum(ctx: int):
+    """(E_B[nshell], dk) of the current state: see the header."""
+    ns, dk = C.c_int32(), C.c_double()
+    _check(lib.mhd_spectrum(ctx, None, 0, C.byref(ns), C.byref(dk)))
+    out = (C.c_double * max(1, ns.value))()
+    _check(lib.mhd_spectrum(ctx, out, ns.value, C.byref(ns), C.byref(dk)))
+    return np.array(out[:ns.value]), dk.value
+
+
+def mhd_spectrum_shells(p: mhd_params):
+    """(nshell, dk, workspace_bytes) for runs of this size (host-only)."""
+    ns, dk, wb = C.c_int32(), C.c_double(), C.c_size_t()
+    _check(lib.mhd_spectrum_shells(C.byref(p), C.byref(ns), C.byref(dk), C.byref(wb)))
+    return ns.value, dk.value, wb.value
+
+
+def mhd_channel_growth_rate(t: Sequence[float], e: Sequence[float]) -> float:
+    ta = np.ascontiguousarray(t, dtype=np.float64)
+    ea = np.ascontiguousarray(e, dtype=np.float64)
+    if ta.shape != ea.shape:
+        raise ValueError("t and e must have the same length")
+    lam = C.c_double()
+    _check(lib.mhd_channel_growth_rate(ta.ctypes.data_as(C.POINTER(C.c_double)),
+                                       ea.ctypes.data_as(C.POINTER(C.c_double)), len(ta),
+                                       C.byref(lam)))
+    return lam.value
+
+
 def mhd_forcing_draw(kf: float, f0: float, sigma: float, seed: int, n: int) -> mhd_forcing:
     out = mhd_forcing()
     _check(lib.mhd_forcing_draw(kf, f0, sigma, seed, n, C.byref(out)))
@@ -447,3 +481,6 @@ class Run:
 
     def diag(self):
         return mhd_get_diag(self.h)
+
+    def spectrum(self):
+        return mhd_spectrum(self.h)

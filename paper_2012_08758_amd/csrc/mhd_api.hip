@@ -631,6 +631,9 @@ void ctx_release(mhd_ctx *c)
     if (c->stream || true) hipStreamSynchronize(c->stream);
     if (c->owns && c->mem) hipFree(c->mem);
     if (c->aux) hipFree(c->aux);
+    if (c->spec_ws) hipFree(c->spec_ws);
+    c->spec_ws = nullptr;
+    c->spec_bytes = 0;
     if (c->h_stage) hipHostFree(c->h_stage);
     if (c->stage_evt) hipEventDestroy(c->stage_evt);
     c->mem = c->aux = c->h_stage = nullptr;

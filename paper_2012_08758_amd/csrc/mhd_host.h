@@ -67,6 +67,9 @@ struct mhd_ctx {
     hipEvent_t stage_evt = nullptr;
     int64_t rcount = 0;      // records written on the device since the last drain
     std::vector<mhd_diag> host_diag;
+    // magnetic spectrum workspace (allocated by the first mhd_spectrum call)
+    void *spec_ws = nullptr;
+    size_t spec_bytes = 0;
 };
 
 namespace mhd {

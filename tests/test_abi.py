@@ -117,3 +117,36 @@ def test_binding_refuses_to_run_without_the_library(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+# ------------------------------------------------------------------ spectrum (host-only parts)
+
+@pytest.mark.parametrize("dims,kw", [((32, 32, 32), {}), ((48, 40, 36), dict(lx=5.0, ly=6.0, lz=4.0)),
+                                     ((45, 28, 50), {}), ((2048, 8, 8), {})])
+def test_spectrum_shells_match_the_oracle(dims, kw):
+    import oracle
+    mhd = _mhd()
+    rp = mi.RunParams(*dims, nu=1e-3, eta=1e-3, **kw)
+    ns, dk, wb = mhd.mhd_spectrum_shells(mhd.params_from(rp))
+    assert ns == oracle.spectrum_nshell(rp)
+    assert dk == 2 * math.pi / max(rp.lx, rp.ly, rp.lz)
+    assert wb >= 48 * (rp.nx // 2 + 1) * rp.ny * rp.nz
+
+
+@pytest.mark.parametrize("dims", [(37, 32, 32), (32, 22, 32), (32, 32, 8192)])
+def test_spectrum_rejects_grids_it_cannot_transform(dims):
+    mhd = _mhd()
+    rp = mi.RunParams(*dims, nu=1e-3, eta=1e-3)
+    with pytest.raises(mhd.MhdError) as ei:
+        mhd.mhd_spectrum_shells(mhd.params_from(rp))
+    assert ei.value.status == mhd.MHD_E_UNSUPPORTED
+
+
+def test_channel_growth_rate_is_half_the_log_slope():
+    mhd = _mhd()
+    t = np.arange(50) * 0.1
+    assert abs(mhd.mhd_channel_growth_rate(t, 3e-9 * np.exp(2 * 0.0173 * t)) - 0.0173) < 1e-12
+    with pytest.raises(mhd.MhdError):
+        mhd.mhd_channel_growth_rate(t[:1], np.ones(1))
+    with pytest.raises(mhd.MhdError):
+        mhd.mhd_channel_growth_rate(t, np.zeros(50))
