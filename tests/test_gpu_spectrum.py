@@ -107,6 +107,31 @@ def test_channel_growth_rate_of_a_decaying_beltrami_field(mhd):
     assert abs(mhd.mhd_growth_rate(diag) - lam) < 1e-10
 
 
+def test_spectrum_of_batched_runs(mhd):
+    """Spectra of runs advanced together in one graph-replayed batch (mixed sizes and
+    precisions) match the oracle's spectra of their states."""
+    specs = [mi.RunParams(16, 16, 16, nu=5e-3, eta=5e-3, precision=8),
+             mi.RunParams(24, 20, 16, nu=2e-3, eta=2e-3, precision=8, upwind=1.0),
+             mi.RunParams(32, 32, 32, nu=1e-3, eta=1e-3, precision=4)]
+    b = mhd.mhd_batch_create([mhd.params_from(rp) for rp in specs])
+    try:
+        ctxs = [mhd.mhd_batch_ctx(b, i) for i in range(len(specs))]
+        for i, (c, rp) in enumerate(zip(ctxs, specs)):
+            st = mi.noise_state(rp, 60 + i, 0.05, 0.1, 0.2, dtype=_dtype(rp.precision))
+            for f in range(7):
+                mhd.mhd_set_field(c, f, np.ascontiguousarray(st[f]))
+            mhd.mhd_set_forcing(c, mi.forcing_schedule(70 + i, 6, 3.0, 0.05, float(i % 2)))
+        mhd.mhd_batch_run(b, 6, True)
+        for i, (c, rp) in enumerate(zip(ctxs, specs)):
+            got = np.empty((7, rp.nz, rp.ny, rp.nx), dtype=_dtype(rp.precision))
+            for f in range(7):
+                mhd.mhd_get_field(c, f, got[f])
+            E, dk = mhd.mhd_spectrum(c)
+            _check(E, dk, rp, got, f"batch run {i}")
+    finally:
+        mhd.mhd_batch_destroy(b)
+
+
 # ------------------------------------------------------------------ full size (512^3)
 
 def test_full_size_beltrami_spectrum_fp64(mhd):
