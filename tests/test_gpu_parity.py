@@ -247,6 +247,35 @@ def test_full_size_sampled_one_step(mhd, n, prec, sigma, nu):
     assert np.all(e <= TOL[prec]), e
 
 
+@pytest.mark.parametrize("n,prec,sigma,nu,checks", [(256, 8, 1.0, 1e-3, (100, 200)),
+                                                    (512, 8, 0.0, 4e-4, (100,)), (512, 4, 0.0, 4e-4, (100,))])
+def test_full_size_sampled_later_steps(mhd, n, prec, sigma, nu, checks):
+    """The 256^3 and 512^3 workloads from their seed field (A noise 1e-5) under the
+    forcing schedule, advanced on the GPU: at steps 100 (and 200) the step is checked
+    against the oracle's step from the GPU's own state before it, at sampled cells."""
+    rp = mi.RunParams(n, n, n, nu=nu, eta=nu, dt=1e-3, precision=prec)
+    recs = mi.forcing_schedule(0, max(checks), 3.0, 0.02, sigma)
+    cells = _sample_cells(rp, 300, n + 1)
+    with mhd.Run(mhd.params_from(rp)) as run:
+        mhd.mhd_init_seed(run.h, 0, 1e-5)
+        run.set_forcing(recs)
+        done = 0
+        for c in checks:
+            run.step(c - 1 - done)
+            before = run.get_state()
+            run.step(1)
+            done = c
+            got = run.get_state().reshape(7, -1)[:, cells].T.astype(np.float64)
+            st64 = before.astype(np.float64)
+            del before
+            want = oracle.step_cells(st64, rp, recs[c - 1], cells)
+            terms = oracle.terms_cells(st64, rp, recs[c - 1], cells).max(axis=0).sum(axis=1)
+            del st64
+            e = np.abs(got - want).max(axis=0) / np.maximum(np.abs(want).max(axis=0), rp.dt * terms)
+            print(f"{n}^3 fp{8 * prec} step {c} sampled e_f: " + " ".join(f"{x:.2e}" for x in e), flush=True)
+            assert np.all(e <= TOL[prec]), (c, e)
+
+
 # ------------------------------------------------------------------ diagnostics
 
 @pytest.mark.parametrize("prec", [8, 4])
