@@ -43,8 +43,11 @@ struct MultiRunner {
     bool own_stream = false;
     std::vector<Group> groups;
     hipEvent_t stage_evt = nullptr;
-    // captured graphs, keyed by number of steps
-    std::map<int64_t, hipGraphExec_t> graphs;
+    // runs of different power-of-two size classes go to separate groups (so that they can
+    // take different numbers of steps per call)
+    bool split_by_size = false;
+    // captured graphs, keyed by the number of steps of every group
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
 
     ~MultiRunner() { clear(); }
 
@@ -101,10 +104,11 @@ struct MultiRunner {
         groups.clear();
         if (!stage_evt && hipEventCreateWithFlags(&stage_evt, hipEventDisableTiming) != hipSuccess)
             return fail(MHD_E_DEVICE, "hipEventCreate failed");
-        std::map<std::tuple<int, int, bool, int>, size_t> index;
+        std::map<std::tuple<int, int, bool, int, int>, size_t> index;
         for (mhd_ctx *c : runs) {
             const int upk = c->p.upwind != 0.0 ? 4 : 0;
-            auto key = std::make_tuple(c->p.precision, c->shape, c->fit, upk);
+            const int cls = split_by_size ? (int)std::floor(std::log2((double)c->ncell)) : 0;
+            auto key = std::make_tuple(c->p.precision, c->shape, c->fit, upk, cls);
             auto it = index.find(key);
             if (it == index.end()) {
                 index[key] = groups.size();
@@ -147,10 +151,14 @@ struct MultiRunner {
         return e;
     }
 
-    hipError_t launch_steps(int64_t m)
+    // Step s of every group that takes more than s steps (mg[g] steps for group g).
+    hipError_t launch_steps(const std::vector<int64_t> &mg)
     {
+        const int64_t m = *std::max_element(mg.begin(), mg.end());
         for (int64_t s = 0; s < m; s++)
-            for (auto &g : groups) {
+            for (size_t gi = 0; gi < groups.size(); gi++) {
+                if (s >= mg[gi]) continue;
+                Group &g = groups[gi];
                 hipError_t e = g.prec == MHD_FP64 ? launch_group_step<double>(g, (int)s)
                                                   : launch_group_step<float>(g, (int)s);
                 if (e != hipSuccess) return e;
@@ -158,11 +166,14 @@ struct MultiRunner {
         return hipSuccess;
     }
 
-    // Stage forcing blocks and descriptors of every run for m steps, enqueue uploads.
-    mhd_status stage(int64_t m)
+    // Stage forcing blocks and descriptors of every run of group g for mg[g] steps,
+    // enqueue the uploads.
+    mhd_status stage(const std::vector<int64_t> &mg)
     {
         if (hipEventSynchronize(stage_evt) != hipSuccess) return fail(MHD_E_DEVICE, "staging event failed");
-        for (auto &g : groups) {
+        for (size_t gi = 0; gi < groups.size(); gi++) {
+            Group &g = groups[gi];
+            const int64_t m = mg[gi];
             for (size_t i = 0; i < g.members.size(); i++) {
                 mhd_ctx *c = g.members[i];
                 if (c->rcount + m > CHUNK) {
@@ -192,14 +203,51 @@ struct MultiRunner {
         return MHD_OK;
     }
 
-    void advance(int64_t m)
+    void advance(const std::vector<int64_t> &mg)
     {
-        for (auto &g : groups)
-            for (mhd_ctx *c : g.members) {
-                c->rcount += m;
-                c->parity ^= (int)(m & 1);
-                c->step += m;
+        for (size_t gi = 0; gi < groups.size(); gi++)
+            for (mhd_ctx *c : groups[gi].members) {
+                c->rcount += mg[gi];
+                c->parity ^= (int)(mg[gi] & 1);
+                c->step += mg[gi];
             }
+    }
+
+    // Advance the runs of group g by mg[g] steps (1 <= mg[g] <= CHUNK), as one captured
+    // graph (replayed for the same step counts) or as plain launches.
+    mhd_status run_chunk(const std::vector<int64_t> &mg, bool use_graph)
+    {
+        if (groups.empty()) return MHD_OK;
+        if (mg.size() != groups.size()) return fail(MHD_E_INVALID, "batch: one step count per group needed");
+        for (int64_t m : mg)
+            if (m < 1 || m > CHUNK) return fail(MHD_E_INVALID, "batch: step counts must lie in [1, CHUNK]");
+        mhd_status st = stage(mg);
+        if (st != MHD_OK) return st;
+        if (use_graph) {
+            auto it = graphs.find(mg);
+            if (it == graphs.end()) {
+                hipGraph_t graph;
+                if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                    return fail(MHD_E_DEVICE, "hipStreamBeginCapture failed");
+                hipError_t e = launch_steps(mg);
+                hipError_t e2 = hipStreamEndCapture(stream, &graph);
+                if (e != hipSuccess || e2 != hipSuccess)
+                    return fail(MHD_E_DEVICE, std::string("graph capture failed: ") +
+                                                  hipGetErrorString(e != hipSuccess ? e : e2));
+                hipGraphExec_t exec;
+                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess)
+                    return fail(MHD_E_DEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(e));
+                it = graphs.emplace(mg, exec).first;
+            }
+            if (hipGraphLaunch(it->second, stream) != hipSuccess) return fail(MHD_E_DEVICE, "graph launch failed");
+        } else {
+            hipError_t e = launch_steps(mg);
+            if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+        }
+        advance(mg);
+        return MHD_OK;
     }
 
     // Advance every run by nsteps (chunks of at most CHUNK steps).
@@ -207,32 +255,8 @@ struct MultiRunner {
     {
         while (nsteps > 0) {
             const int64_t m = std::min<int64_t>(nsteps, CHUNK);
-            mhd_status st = stage(m);
+            mhd_status st = run_chunk(std::vector<int64_t>(groups.size(), m), use_graph);
             if (st != MHD_OK) return st;
-            if (use_graph) {
-                auto it = graphs.find(m);
-                if (it == graphs.end()) {
-                    hipGraph_t graph;
-                    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                        return fail(MHD_E_DEVICE, "hipStreamBeginCapture failed");
-                    hipError_t e = launch_steps(m);
-                    hipError_t e2 = hipStreamEndCapture(stream, &graph);
-                    if (e != hipSuccess || e2 != hipSuccess)
-                        return fail(MHD_E_DEVICE, std::string("graph capture failed: ") +
-                                                      hipGetErrorString(e != hipSuccess ? e : e2));
-                    hipGraphExec_t exec;
-                    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                    (void)hipGraphDestroy(graph);
-                    if (e != hipSuccess)
-                        return fail(MHD_E_DEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(e));
-                    it = graphs.emplace(m, exec).first;
-                }
-                if (hipGraphLaunch(it->second, stream) != hipSuccess) return fail(MHD_E_DEVICE, "graph launch failed");
-            } else {
-                hipError_t e = launch_steps(m);
-                if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
-            }
-            advance(m);
             nsteps -= m;
         }
         return MHD_OK;
@@ -278,6 +302,10 @@ static double pct(std::vector<double> v, double q)
 }
 
 }  // namespace mhd
+
+// Fixed cost of one step of a run group, in cells: its four launches cost about as much
+// as advancing this many cells.
+constexpr double TICK_OVERHEAD_CELLS = 2e5;
 
 struct mhd_server {
     size_t budget = 0;
@@ -341,8 +369,12 @@ void mhd_server::loop()
             for (int64_t id : active) act.push_back(reqs[id].get());
         }
         // 1. the tick of the active set goes to the device (replayed as a captured graph
-        //    while the set is unchanged; rebuilt after an admission or a retirement)
-        int64_t k = 0;
+        //    while the set and the step counts are unchanged; rebuilt after an admission
+        //    or a retirement).  Runs are grouped by size class; the costliest group takes
+        //    steps_per_tick steps and every other group as many more as makes its share of
+        //    the tick about as long, so small runs are not held to the pace of large ones.
+        std::vector<int64_t> kq;
+        std::map<mhd_ctx *, int64_t> kof;
         mhd_status st = MHD_OK;
         if (!act.empty()) {
             if (set_changed) {
@@ -354,10 +386,22 @@ void mhd_server::loop()
                 }
                 set_changed = false;
             }
-            k = steps_per_tick;
-            for (Request *r : act) k = std::min<int64_t>(k, r->nsteps - r->steps_done);
+            std::map<mhd_ctx *, int64_t> left;
+            for (Request *r : act) left[r->ctx] = r->nsteps - r->steps_done;
+            std::vector<double> cost(mr.groups.size(), TICK_OVERHEAD_CELLS);
+            for (size_t gi = 0; gi < mr.groups.size(); gi++)
+                for (mhd_ctx *c : mr.groups[gi].members) cost[gi] += (double)c->ncell;
+            const double cmax = *std::max_element(cost.begin(), cost.end());
+            kq.resize(mr.groups.size());
+            for (size_t gi = 0; gi < mr.groups.size(); gi++) {
+                int64_t k = std::llround((double)steps_per_tick * cmax / cost[gi]);
+                k = std::max<int64_t>(1, std::min<int64_t>(k, CHUNK));
+                for (mhd_ctx *c : mr.groups[gi].members) k = std::min(k, left[c]);
+                kq[gi] = k;
+                for (mhd_ctx *c : mr.groups[gi].members) kof[c] = k;
+            }
             if (have_ev) (void)hipEventRecord(ev0, mr.stream);
-            st = mr.run(k, true);
+            st = mr.run_chunk(kq, true);
             if (have_ev) (void)hipEventRecord(ev1, mr.stream);
         }
         const double ta = now();
@@ -408,8 +452,6 @@ void mhd_server::loop()
             set_changed = true;
         }
         if (act.empty()) continue;
-        double cells = 0;
-        for (Request *r : act) cells += (double)r->ctx->ncell;
         // a run whose state went non-finite is evicted at the tick where it shows
         std::vector<Request *> finished;
         for (Request *r : act) {
@@ -421,9 +463,11 @@ void mhd_server::loop()
             std::lock_guard<std::mutex> lk(mu);
             ticks++;
             busy_s += tick_ms * 1e-3;
-            cell_substeps += 3.0 * (double)k * cells;
-            const double per = tick_ms / (double)k;
             for (Request *r : act) {
+                const int64_t k = kof[r->ctx];
+                cell_substeps += 3.0 * (double)k * (double)r->ctx->ncell;
+                // a run's steps are spread evenly over the tick it advanced in
+                const double per = tick_ms / (double)k;
                 r->steps_done += k;
                 for (int64_t q = 0; q < k; q++) step_lat_ms.push_back(per);
                 if (r->steps_done >= r->nsteps) finished.push_back(r);
@@ -536,6 +580,7 @@ mhd_status mhd_server_create(size_t hbm_budget, int32_t max_slots, int32_t steps
     s->budget = hbm_budget;
     s->max_slots = max_slots;
     s->steps_per_tick = steps_per_tick;
+    s->mr.split_by_size = true;
     mhd_status st = s->mr.init_stream(hip_stream);
     if (st != MHD_OK) {
         delete s;
