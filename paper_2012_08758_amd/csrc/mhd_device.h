@@ -840,6 +840,25 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         }
         voff[v] = (uint32_t)sizeof(T) * ((uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz));
     }
+    // ln rho, u_x and A_x enter only through derivatives along the axes and in the xy and
+    // xz planes: their boxes need no row that lies outside the tile in both y and z (the
+    // four 3x3 corner blocks of rows).  Those vectors re-read an address another lane of
+    // the same wave instruction reads anyway (or, if the whole instruction is corner rows,
+    // one common address), so they add no line requests; the instruction count, and with
+    // it every wait count, is unchanged.  Their LDS slots hold unused values.
+    uint32_t voffx[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        int qv = v * NT + tid;
+        if (qv >= NVEC) qv = NVEC - 1;
+        const int q = qv * EPL;
+        const int by = (q / XW) % YW, bz = q / SZ;
+        const bool corner = (by < 3 || by >= 3 + TY) && (bz < 3 || bz >= 3 + TZ);
+        const uint64_t need = __ballot(!corner);
+        const int src = need ? __ffsll((unsigned long long)need) - 1 : 0;
+        const uint32_t sub = __shfl(voff[v], src, 64);
+        voffx[v] = corner ? sub : voff[v];
+    }
 
     int cidx[CZ], icell[CZ];
     uint32_t gcell[CZ];
@@ -867,8 +886,8 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     // from its own field's box
     if constexpr (STORE)
         Frc::copy((const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride, lds[2], lane, x0s, y0, z0, nx, ny, nz);
-    ring_copy<T, NV, NT, EPL>(in[0], lds[0], voff, wave);
-    ring_copy<T, NV, NT, EPL>(in[1], lds[1], voff, wave);
+    ring_copy<T, NV, NT, EPL>(in[0], lds[0], voffx, wave);
+    ring_copy<T, NV, NT, EPL>(in[1], lds[1], voffx, wave);
 
     Cells<T, CZ> C;
     ring_barrier<NV>();
@@ -893,7 +912,7 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
     if constexpr (UPW) pin_up6(C);
 
     ring_barrier<NV>();
-    ring_copy<T, NV, NT, EPL>(in[4], lds[1], voff, wave);
+    ring_copy<T, NV, NT, EPL>(in[4], lds[1], voffx, wave);
     absorb<T, 2, SY, SZ, CZ, DIAG, true, UPW>(C, lds[2], cidx, K, dc);
     pin_pend(C, 3);
     if constexpr (UPW) pin_up6(C);

@@ -438,6 +438,27 @@ def test_server_continuous_batching_equals_alone(mhd):
         mhd.mhd_server_destroy(srv)
 
 
+def test_server_small_runs_keep_their_own_pace(mhd):
+    """A small run submitted after a large one with as many steps finishes first: each
+    size class takes steps in proportion to its cost, not one step per large step."""
+    big = mi.RunParams(64, 64, 64, nu=3e-3, eta=3e-3, precision=4)
+    small = mi.RunParams(16, 16, 16, nu=3e-3, eta=3e-3, precision=4)
+    srv = mhd.mhd_server_create(1 << 30, 4, 4)
+    try:
+        mhd.mhd_server_start(srv)
+        ib = mhd.mhd_server_submit(srv, mhd.params_from(big), 1, 1e-3, 3.0, 0.02, 0.0, 300)
+        is_ = mhd.mhd_server_submit(srv, mhd.params_from(small), 2, 1e-3, 3.0, 0.02, 1.0, 300)
+        mhd.mhd_server_wait(srv, ib, 120.0)
+        mhd.mhd_server_wait(srv, is_, 120.0)
+        rb, rs = mhd.mhd_server_poll(srv, ib), mhd.mhd_server_poll(srv, is_)
+        assert rb.state == rs.state == mhd.MHD_RUN_DONE
+        assert rb.steps_done == rs.steps_done == 300
+        print(f"large done at {rb.t_done - rb.t_submit:.3f} s, small at {rs.t_done - rs.t_submit:.3f} s", flush=True)
+        assert rs.t_done < rb.t_done
+    finally:
+        mhd.mhd_server_destroy(srv)
+
+
 def test_server_evicts_a_run_that_goes_nonfinite(mhd):
     """A run with an unstable time step is flagged and evicted; a co-resident run is unaffected."""
     good = mi.RunParams(16, 16, 16, nu=3e-3, eta=3e-3, precision=8)
