@@ -860,22 +860,9 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         voffx[v] = corner ? sub : voff[v];
     }
 
-    int cidx[CZ], icell[CZ];
-    uint32_t gcell[CZ];
-    bool inside[CZ];
-    int gpos[CZ][3];
+    int cidx[CZ];
 #pragma unroll
-    for (int c = 0; c < CZ; c++) {
-        const int lz = lz0 + c * ZS;
-        cidx[c] = (lz + 3) * SZ + (ly + 3) * SY + (lx + 4);
-        icell[c] = lx + TX * (ly + TY * lz);
-        gpos[c][0] = x0s + lx >= nx ? x0s + lx - nx : x0s + lx;
-        gpos[c][1] = y0 + ly;
-        gpos[c][2] = z0 + lz;
-        inside[c] = x0 + lx < nx && gpos[c][1] < ny && gpos[c][2] < nz;
-        gcell[c] = inside[c] ? (uint32_t)gpos[c][0] + (uint32_t)nx * ((uint32_t)gpos[c][1] + (uint32_t)ny * (uint32_t)gpos[c][2])
-                             : 0u;
-    }
+    for (int c = 0; c < CZ; c++) cidx[c] = (lz0 + c * ZS + 3) * SZ + (ly + 3) * SY + (lx + 4);
 
     KRegsFor<T, UPW> K;
     K.load(r.c);
@@ -938,6 +925,24 @@ k_pipe(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, i
         ring_barrier<0>();
     }
     absorb<T, 6, SY, SZ, CZ, DIAG, true, UPW>(C, lds[0], cidx, K, dc);
+    // the cells' global positions, computed here so that they hold no registers during
+    // the passes
+    __builtin_amdgcn_sched_barrier(0);
+    int icell[CZ];
+    uint32_t gcell[CZ];
+    bool inside[CZ];
+    int gpos[CZ][3];
+#pragma unroll
+    for (int c = 0; c < CZ; c++) {
+        const int lz = lz0 + c * ZS;
+        icell[c] = lx + TX * (ly + TY * lz);
+        gpos[c][0] = x0s + lx >= nx ? x0s + lx - nx : x0s + lx;
+        gpos[c][1] = y0 + ly;
+        gpos[c][2] = z0 + lz;
+        inside[c] = x0 + lx < nx && gpos[c][1] < ny && gpos[c][2] < nz;
+        gcell[c] = inside[c] ? (uint32_t)gpos[c][0] + (uint32_t)nx * ((uint32_t)gpos[c][1] + (uint32_t)ny * (uint32_t)gpos[c][2])
+                             : 0u;
+    }
     if constexpr (STORE && SUB != 0) {
         ring_barrier<0>();
 #pragma unroll
