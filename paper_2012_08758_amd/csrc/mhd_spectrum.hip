@@ -256,6 +256,7 @@ __global__ __launch_bounds__(NT) void k_spec_bin(const double2 *__restrict__ W, 
                 const double ax = __dmul_rn((double)m, a.rx);
                 const double q = __dadd_rn(__dadd_rn(__dmul_rn(ax, ax), y2), z2);
                 s = (int)floor(__dadd_rn(__dsqrt_rn(q), 0.5));
+                s = s < a.nsh ? s : a.nsh - 1;  // never above the corner's shell; kept in range regardless
             }
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -335,8 +336,10 @@ static Geometry geometry(const mhd_params &p)
     g.ry = lmax / p.ly;
     g.rz = lmax / p.lz;
     // shell of the corner wavevector (n_a / 2 per axis), same operation order as the bins
+    // (squares in statements of their own, so that no multiply-add is contracted)
     const double ax = (double)(p.nx / 2) * g.rx, ay = (double)(p.ny / 2) * g.ry, az = (double)(p.nz / 2) * g.rz;
-    g.nsh = (int)std::floor(std::sqrt(ax * ax + ay * ay + az * az) + 0.5) + 1;
+    const double x2 = ax * ax, y2 = ay * ay, z2 = az * az;
+    g.nsh = (int)std::floor(std::sqrt((x2 + y2) + z2) + 0.5) + 1;
     return g;
 }
 
