@@ -146,6 +146,28 @@ def spectrum_timing(mhd, h, n, prec, reps=5):
                 nshell=len(E), dk=dk, em_from_spectrum=float(np.sum(E) * dk / (2 * np.pi) ** 3))
 
 
+def growth_run(mhd, n=256, steps=200):
+    """The 256^3 helical workload: FP64, forcing at kf = 3 with helicity 1, f0 = 0.02,
+    nu = eta = 1e-3, seed field 1e-5, 200 steps; FP64 diagnostics of every step and the
+    growth-rate fits of ln B_rms over steps 1-200 and 101-200."""
+    p = mhd.make_params(n, nu=1e-3, eta=1e-3, dt=1e-3, precision=mhd.MHD_FP64)
+    h = mhd.mhd_create(p)
+    try:
+        mhd.mhd_init_seed(h, 0, 1e-5)
+        mhd.mhd_set_forcing_random(h, 3.0, 0.02, 1.0, 0)
+        kms, step_ms = mhd.mhd_step_timed(h, steps)
+        mhd.mhd_reduce(h)
+        diag = mhd.mhd_get_diag(h)
+    finally:
+        mhd.mhd_destroy(h)
+    return dict(steps=steps, ms_per_step=float(np.mean(step_ms)),
+                cell_substeps_per_s=3.0 * n ** 3 / (float(np.mean(step_ms)) * 1e-3),
+                lambda_steps_1_200=mhd.mhd_growth_rate(diag, 1, len(diag)),
+                lambda_steps_101_200=mhd.mhd_growth_rate(diag, 101, len(diag)),
+                em_first=diag[0]["em"], em_last=diag[-1]["em"], urms_last=diag[-1]["urms"],
+                nonfinite=max(d["nonfinite"] for d in diag))
+
+
 def shape_sweep(mhd, n, steps=3):
     out = {}
     for prec in (mhd.MHD_FP64, mhd.MHD_FP32):
@@ -331,6 +353,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-spectrum", action="store_true")
+    ap.add_argument("--no-growth", action="store_true")
     ap.add_argument("--serve-runs", type=int, default=40)
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--cpu-nz", type=int, default=64)
@@ -386,6 +409,12 @@ def main():
         finally:
             mhd.mhd_destroy(r64["handle"])
             mhd.mhd_destroy(r32["handle"])
+    grow = None
+    if not args.no_growth:
+        log("[bench] 256^3 helical FP64, 200 steps")
+        grow = growth_run(mhd)
+        log(f"[bench] 256^3: {grow['ms_per_step']:.2f} ms/step, lambda(1-200) {grow['lambda_steps_1_200']:.4e}, "
+            f"lambda(101-200) {grow['lambda_steps_101_200']:.4e}")
     ens = None
     if not args.no_ensemble:
         log("[bench] ensemble: 48 runs x %d steps" % args.ensemble_steps)
@@ -450,6 +479,7 @@ def main():
         "ensemble": ens,
         "serving": srv,
         "spectrum": spec,
+        "growth_256": grow,
     }
     if sweep is not None:
         out["shape_sweep"] = sweep

@@ -323,6 +323,34 @@ def test_beltrami_growth_rate_on_gpu(mhd):
     assert abs(lam - math.log(abs(G)) / rp.dt) < 1e-10
 
 
+def test_growth_rate_windows_match_the_oracle(mhd):
+    """The 256^3 workload's recipe at 32^3 (FP64, helical forcing at kf = 3, f0 = 0.02,
+    nu = eta = 1e-3, seed field 1e-5, 200 steps): the device's B_rms series and the
+    growth-rate fits over steps 1-200 and 101-200 agree with the oracle's run."""
+    rp = mi.RunParams(32, 32, 32, nu=1e-3, eta=1e-3, dt=1e-3, precision=8)
+    st = mi.ic_seed_noise(rp, 0, 1e-5)
+    recs = mi.forcing_schedule(0, 200, 3.0, 0.02, 1.0)
+    _, diag = gpu_run(mhd, rp, st, recs)
+    assert len(diag) == 201
+    cur = st.astype(np.float64)
+    t, br = [], []
+    for n in range(201):
+        d = oracle.diag(cur, rp)
+        t.append(n * rp.dt)
+        br.append(d["brms"])
+        if n < 200:
+            cur, _ = oracle.step(cur, rp, [recs[n]])
+    gb = np.array([r["brms"] for r in diag])
+    rel = np.max(np.abs(gb - np.array(br)) / np.array(br))
+    print(f"B_rms series max relative difference over 200 steps: {rel:.2e}", flush=True)
+    assert rel <= 1e-11
+    for i0 in (1, 101):
+        lg = mhd.mhd_growth_rate(diag, i0, 201)
+        lo = oracle.growth_rate(t, br, i0, 201)
+        print(f"lambda over steps {i0}-200: device {lg:.12e} oracle {lo:.12e}", flush=True)
+        assert abs(lg - lo) <= 1e-10
+
+
 # ------------------------------------------------------------------ runtime properties
 
 def test_init_seed_matches_input_generator(mhd):
