@@ -453,7 +453,7 @@ template <typename T, int TX, int TY, int TZ, int CZ, bool FIT>
 static hipError_t launch_pipe(int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles, int step,
                               hipStream_t st)
 {
-    constexpr int W = 2;
+    constexpr int W = pipe_waves<T, TX, TY, TZ, CZ>();
     const dim3 grid(ntiles), block(TX * TY * (TZ / CZ));
     switch (kind) {
     case 0: hipLaunchKernelGGL((k_pipe<T, TX, TY, TZ, CZ, 0, true, true, W, FIT>), grid, block, 0, st, runs, tiles, step); break;

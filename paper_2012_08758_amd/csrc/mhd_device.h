@@ -763,6 +763,24 @@ constexpr int pipe_lds_bytes()
     return 3 * ((NVEC + NT - 1) / NT) * NT * 16;
 }
 
+// Minimum waves per SIMD the ring kernel is compiled for (its register budget is
+// 512 / this).  FP64 and two-cell kernels need up to 256 registers: 2.  One-cell FP32
+// kernels fit in 80: as many whole work-groups as the LDS holds, up to 6 waves per
+// SIMD (three 512-thread groups of 48 KB; more groups or waves would force spills).
+template <typename T, int TX, int TY, int TZ, int CZ>
+constexpr int pipe_waves()
+{
+    if (sizeof(T) != 4 || CZ != 1) return 2;
+    constexpr int wpb = TX * TY * TZ / 64;
+    constexpr int lds = pipe_lds_bytes<T, TX, TY, TZ, CZ>();
+    int best = 2;
+    for (int b = 1; b * lds <= 160 * 1024; b++) {
+        const int w = b * wpb;
+        if (w % 4 == 0 && w / 4 <= 6 && w / 4 > best) best = w / 4;
+    }
+    return best;
+}
+
 // Every read of the pipeline is a direct-to-LDS copy, which the compiler's wait
 // analysis does not see; a register load issued before such copies would get a
 // full drain (vmcnt(0)) in front of its first use, stalling the prefetch.  So the
