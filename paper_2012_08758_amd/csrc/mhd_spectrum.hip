@@ -152,26 +152,47 @@ __global__ __launch_bounds__(NTF) void k_fft_x(const T *__restrict__ a0, const T
     const long long line0 = (long long)blockIdx.x << (lp + 1);
     for (int i = threadIdx.x; i < n; i += NTF) tw[i] = twg[i];
     double *bd = reinterpret_cast<double *>(buf);
+    // the block's 2P lines are one contiguous run of the array; (line, t) of element i
+    // advance by a fixed step instead of a division per element
     const int tot = n << (lp + 1);
-    for (int i = threadIdx.x; i < tot; i += NTF) {
-        const int rl = i / n, t = i - rl * n;
-        const long long line = line0 + rl;
-        const double v = line < nlines ? (double)src[line * n + t] : 0.0;
-        bd[2 * ((t << lp) + (rl >> 1)) + (rl & 1)] = v;
+    const T *blk = src + line0 * n;
+    const long long valid = (nlines - line0) * n;  // elements of the run inside the array
+    {
+        const int drl = NTF / n, dt = NTF - drl * n;
+        int rl = (int)threadIdx.x / n, t = (int)threadIdx.x - rl * n;
+        for (int i = threadIdx.x; i < tot; i += NTF) {
+            const double v = i < valid ? (double)blk[i] : 0.0;
+            bd[2 * ((t << lp) + (rl >> 1)) + (rl & 1)] = v;
+            t += dt;
+            rl += drl;
+            if (t >= n) {
+                t -= n;
+                rl++;
+            }
+        }
     }
     __syncthreads();
     run_stages<LC>(buf, tw, pl);
-    double2 *dst = W + c * cstride;
+    double2 *dst = W + c * cstride + line0 * nh;
     const int toth = nh << (lp + 1);
-    for (int i = threadIdx.x; i < toth; i += NTF) {
-        const int rl = i / nh, m = i - rl * nh;
-        const long long line = line0 + rl;
-        if (line < nlines) {
-            const int p = rl >> 1;
-            const double2 z = buf[(m << lp) + p];
-            const double2 w = buf[((m == 0 ? 0 : n - m) << lp) + p];
-            dst[line * nh + m] = (rl & 1) ? make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x))
-                                          : make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
+    const long long validh = (nlines - line0) * nh;
+    {
+        const int drl = NTF / nh, dm = NTF - drl * nh;
+        int rl = (int)threadIdx.x / nh, m = (int)threadIdx.x - rl * nh;
+        for (int i = threadIdx.x; i < toth; i += NTF) {
+            if (i < validh) {
+                const int p = rl >> 1;
+                const double2 z = buf[(m << lp) + p];
+                const double2 w = buf[((m == 0 ? 0 : n - m) << lp) + p];
+                dst[i] = (rl & 1) ? make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x))
+                                  : make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
+            }
+            m += dm;
+            rl += drl;
+            if (m >= nh) {
+                m -= nh;
+                rl++;
+            }
         }
     }
 }
