@@ -51,14 +51,14 @@ const Shape SHAPES[NSHAPES] = {
     {8, 8, 4, 1, false},    // 2: 256 threads, small grids
     {16, 8, 8, 2, false},   // 3: 512 threads, 1024 cells, 4.2
     {32, 4, 4, 1, false},   // 4: 512 threads, 7.4
-    {16, 16, 4, 2, false},  // 5: 512 threads, 1024 cells, 4.7
+    {32, 4, 8, 2, false},   // 5: 512 threads, 1024 cells, 5.2
     // direct-to-LDS ring kernel: nx a multiple of 16 / sizeof(value), 16-byte aligned fields
     {16, 8, 4, 1, true},    // 6
     {32, 8, 4, 1, true},    // 7
     {8, 8, 4, 1, true},     // 8
     {16, 8, 8, 2, true},    // 9
     {32, 4, 4, 1, true},    // 10
-    {16, 16, 4, 2, true},   // 11
+    {32, 4, 8, 2, true},    // 11
     // z-marching column kernel (ring per field in LDS): the tile divides the grid
     {16, 8, 4, 1, true, true},  // 12: FP32 only (the FP64 rings do not fit the LDS)
     {8, 8, 4, 1, true, true},   // 13
@@ -112,10 +112,10 @@ int default_shape(const mhd_params &p, bool aligned)
         if (it != g_tuned.end()) want = it->second;
     }
     if (want < 0) {
-        // measured at 512^3: 16x8x8/2 is the fastest FP64 ring shape, 32x4x4/1 the
+        // measured at 512^3: 16x8x8/2 is the fastest FP64 ring shape, 32x4x8/2 the
         // fastest FP32 one; small grids want the small tile (more work-groups)
         const double n = (double)p.nx * p.ny * p.nz;
-        want = n <= 64.0 * 64 * 64 ? 8 : (p.precision == MHD_FP64 ? 9 : 10);
+        want = n <= 64.0 * 64 * 64 ? 8 : (p.precision == MHD_FP64 ? 9 : 11);
     }
     while (!shape_eligible(p, want, aligned)) want = shape_fallback(want);
     return want;
@@ -509,13 +509,13 @@ hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs,
     case 2: return launch_shape<T, 8, 8, 4, 1>(kind, runs, tiles, ntiles, step, st);
     case 3: return launch_shape<T, 16, 8, 8, 2>(kind, runs, tiles, ntiles, step, st);
     case 4: return launch_shape<T, 32, 4, 4, 1>(kind, runs, tiles, ntiles, step, st);
-    case 5: return launch_shape<T, 16, 16, 4, 2>(kind, runs, tiles, ntiles, step, st);
+    case 5: return launch_shape<T, 32, 4, 8, 2>(kind, runs, tiles, ntiles, step, st);
     case 6: return launch_pipe_fit<T, 16, 8, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
     case 7: return launch_pipe_fit<T, 32, 8, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
     case 8: return launch_pipe_fit<T, 8, 8, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
     case 9: return launch_pipe_fit<T, 16, 8, 8, 2>(fit, kind, runs, tiles, ntiles, step, st);
     case 10: return launch_pipe_fit<T, 32, 4, 4, 1>(fit, kind, runs, tiles, ntiles, step, st);
-    case 11: return launch_pipe_fit<T, 16, 16, 4, 2>(fit, kind, runs, tiles, ntiles, step, st);
+    case 11: return launch_pipe_fit<T, 32, 4, 8, 2>(fit, kind, runs, tiles, ntiles, step, st);
     case 12: return launch_march<T, 16, 8, 4>(kind, runs, tiles, ntiles, step, st);
     default: return launch_march<T, 8, 8, 4>(kind, runs, tiles, ntiles, step, st);
     }

@@ -764,14 +764,15 @@ constexpr int pipe_lds_bytes()
 }
 
 // Minimum waves per SIMD the ring kernel is compiled for (its register budget is
-// 512 / this).  FP64 and two-cell kernels need up to 256 registers: 2.  One-cell FP32
-// kernels fit in 80: as many whole work-groups as the LDS holds, up to 6 waves per
-// SIMD (three 512-thread groups of 48 KB; more groups or waves would force spills).
+// 512 / this).  FP64 kernels need up to 256 registers: 2.  FP32 kernels: as many whole
+// work-groups as the LDS holds, up to 6 waves per SIMD (one-cell kernels fit in 80
+// registers: three 512-thread groups of 48 KB; two-cell kernels in 128: two groups of
+// 72 KB; more would force spills).
 template <typename T, int TX, int TY, int TZ, int CZ>
 constexpr int pipe_waves()
 {
-    if (sizeof(T) != 4 || CZ != 1) return 2;
-    constexpr int wpb = TX * TY * TZ / 64;
+    if (sizeof(T) != 4) return 2;
+    constexpr int wpb = TX * TY * (TZ / CZ) / 64;
     constexpr int lds = pipe_lds_bytes<T, TX, TY, TZ, CZ>();
     int best = 2;
     for (int b = 1; b * lds <= 160 * 1024; b++) {
