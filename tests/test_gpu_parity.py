@@ -351,6 +351,27 @@ def test_growth_rate_windows_match_the_oracle(mhd):
         assert abs(lg - lo) <= 1e-10
 
 
+def test_autotuner_picks_a_shape_that_runs_correctly(mhd):
+    """mhd_autotune times every eligible tile shape on a scratch run and pins the fastest
+    for the grid; a run created afterwards uses it and still matches the oracle."""
+    rp = mi.RunParams(48, 40, 32, nu=2e-3, eta=2e-3, dt=1e-3, precision=4)
+    p = mhd.params_from(rp)
+    names = {mhd.mhd_tile_shape_name(i) for i in range(mhd.mhd_num_tile_shapes())}
+    try:
+        best = mhd.mhd_autotune(p, 2)
+        chosen = mhd.mhd_tile_config(p)
+        print(f"autotuned {chosen}: {best:.3f} ms per step", flush=True)
+        assert best > 0 and any(chosen.startswith(n.split("+")[0]) for n in names)
+        st = mi.noise_state(rp, 17, 0.1, 0.1, 0.1, dtype=np.float32)
+        recs = mi.forcing_schedule(9, 2, 3.0, 0.05, 1.0)
+        got, _ = gpu_run(mhd, rp, st, recs, per_step=True)
+        want, scales = oracle_per_step(st, rp, recs)
+        for n in range(2):
+            check_step(got[n], want[n], scales[n], rp, f"autotuned {chosen} step {n + 1}")
+    finally:
+        mhd.mhd_set_tile_shape(p, -1)
+
+
 # ------------------------------------------------------------------ runtime properties
 
 def test_init_seed_matches_input_generator(mhd):
