@@ -146,6 +146,26 @@ def spectrum_timing(mhd, h, n, prec, reps=5):
                 nshell=len(E), dk=dk, em_from_spectrum=float(np.sum(E) * dk / (2 * np.pi) ** 3))
 
 
+def upwind_run(mhd, n, prec, steps=20, warmup=3):
+    """The 512^3 single run with full upwinding of the continuity advection (the
+    paper's production setting; its benchmarks had it off): time per step and the
+    substep-2 launch against the HBM roofline."""
+    p = mhd.make_params(n, nu=4e-4, eta=4e-4, dt=1e-3, precision=prec, upwind=1.0)
+    h = mhd.mhd_create(p)
+    try:
+        mhd.mhd_init_seed(h, 0, 1e-5)
+        mhd.mhd_set_forcing_random(h, 3.0, 0.02, 0.0, 0)
+        mhd.mhd_step(h, warmup)
+        mhd.mhd_sync(h)
+        kms, step_ms = mhd.mhd_step_timed(h, steps)
+    finally:
+        mhd.mhd_destroy(h)
+    sub2 = 21.0 * prec * float(n) ** 3
+    return dict(steps=steps, ms_per_step=float(np.mean(step_ms)), substep2_ms=kms[1],
+                substep2_gbs=sub2 / (kms[1] * 1e-3) / 1e9,
+                roofline_frac=sub2 / (kms[1] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+
 def growth_run(mhd, n=256, steps=200):
     """The 256^3 helical workload: FP64, forcing at kf = 3 with helicity 1, f0 = 0.02,
     nu = eta = 1e-3, seed field 1e-5, 200 steps; FP64 diagnostics of every step and the
@@ -354,6 +374,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-spectrum", action="store_true")
     ap.add_argument("--no-growth", action="store_true")
+    ap.add_argument("--no-upwind", action="store_true")
     ap.add_argument("--serve-runs", type=int, default=40)
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--cpu-nz", type=int, default=64)
@@ -409,6 +430,12 @@ def main():
         finally:
             mhd.mhd_destroy(r64["handle"])
             mhd.mhd_destroy(r32["handle"])
+    upw = None
+    if not args.no_upwind:
+        upw = {}
+        for name, prec in (("fp64", mhd.MHD_FP64), ("fp32", mhd.MHD_FP32)):
+            upw[name] = upwind_run(mhd, args.n, prec)
+            log(f"[bench] {args.n}^3 {name} with upwinding: {upw[name]['ms_per_step']:.2f} ms/step")
     grow = None
     if not args.no_growth:
         log("[bench] 256^3 helical FP64, 200 steps")
@@ -480,6 +507,7 @@ def main():
         "serving": srv,
         "spectrum": spec,
         "growth_256": grow,
+        "upwinding": upw,
     }
     if sweep is not None:
         out["shape_sweep"] = sweep
