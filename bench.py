@@ -245,7 +245,9 @@ def ensemble(mhd, nsteps=500, alone_steps=None):
         for c, r in zip(ctxs, runs):
             mhd.mhd_init_seed(c, r["seed"], r["a_noise"])
             mhd.mhd_set_forcing_random(c, r["kf"], r["f0"], r["sigma"], r["seed"])
-        mhd.mhd_batch_run(b, 2, True)       # capture + warm-up
+        # warm-up: the first call of a step count captures its graph; the timed call
+        # replays it (all nsteps <= 512 steps as one graph launch)
+        mhd.mhd_batch_run(b, nsteps, True)
         for c in ctxs:
             mhd.mhd_sync(c)
         t0 = time.perf_counter()

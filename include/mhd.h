@@ -267,7 +267,7 @@ typedef struct {
  * finished runs leave and free their memory at tick boundaries.  Active runs are
  * grouped by precision, tile shape and power-of-two size class: the group with the
  * most cells advances steps_per_tick steps per tick, every other group about
- * steps_per_tick * (its cost ratio) steps (at most 256, never past a run's end), so
+ * steps_per_tick * (its cost ratio) steps (at most 512, never past a run's end), so
  * each group's share of a tick takes about as long and small runs progress at their
  * own speed.  The loop runs on its own host thread between mhd_server_start and _stop. */
 mhd_status mhd_server_create(size_t hbm_budget, int32_t max_slots, int32_t steps_per_tick,

@@ -21,7 +21,7 @@ constexpr int NSHAPES = 14;
 extern const Shape SHAPES[NSHAPES];
 
 // steps whose forcing blocks and diagnostic records are staged at once
-constexpr int CHUNK = 256;
+constexpr int CHUNK = 512;
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
