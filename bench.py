@@ -1,6 +1,8 @@
 """Benchmark: RK3 cell-substeps/s and HBM roofline fraction of the 512^3 single run
-(FP64, with FP32 side by side), the batched 48-run ensemble, and a served Poisson
-run stream, on one MI355X.  Prints ONE JSON line.
+(FP64, with FP32 side by side), the magnetic spectrum, the 512^3 runs with
+upwinding, the 256^3 helical run with its growth-rate fits, the batched 48-run
+ensemble, and a served Poisson run stream, on one MI355X, beside the FP64 CPU oracle
+timed on a sample of the 512^3 work.  Prints ONE JSON line.
 
 Timing follows the paper's benchmark protocol (Appendix A): warm-up steps, then
 timed steps, per-step time reported with its 90th percentile next to the mean.
