@@ -80,7 +80,8 @@ typedef struct {
     double f0;
 } mhd_forcing;
 
-/* Global diagnostics of the state at the start of step `step` (time t):
+/* Global diagnostics of the state at the start of step `step` (time t = step * dt,
+ * rounded once, so records do not depend on how the steps were split into calls):
  *   em = <|B|^2>/2, ek = <rho |u|^2>/2, urms = sqrt<|u|^2>, brms = sqrt<|B|^2>,
  *   umax = max |u|, lnrho_mean = <ln rho>, b_mean = <B>, nonfinite = number of
  * cells holding a NaN/Inf in any field.  B uses the same sixth-order curl as the

@@ -683,7 +683,6 @@ void fill_desc(const mhd_ctx *c, RunDesc<T> &d, int parity0, int64_t step0, cons
     d.nb2 = c->nb2;
     d.records = records;
     d.step0 = (double)step0;
-    d.t0 = (double)step0 * c->p.dt;
     d.dt = c->p.dt;
 }
 template void fill_desc<float>(const mhd_ctx *, RunDesc<float> &, int, int64_t, const float *, double *, double *, int);

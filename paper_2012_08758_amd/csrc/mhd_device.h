@@ -111,7 +111,7 @@ struct RunDesc {
     int seg;            // z-marching kernel: planes per z-segment of a column
     double *records;    // [batch step][DREC]
     double step0;       // global step index of batch step 0
-    double t0, dt;
+    double dt;
 };
 
 struct TileEnt {
@@ -1507,7 +1507,7 @@ __global__ void __launch_bounds__(64) k_finalize2(const RunDesc<T> *__restrict__
         const double n = (double)r.nx * (double)r.ny * (double)r.nz;
         G<double> *o = (G<double> *)r.records + (size_t)step * DREC;
         o[0] = r.step0 + (double)step;
-        o[1] = r.t0 + (double)step * r.dt;
+        o[1] = (r.step0 + (double)step) * r.dt;  // one rounding: the same for any split into calls
         o[2] = 0.5 * res[0] / n;
         o[3] = 0.5 * res[2] / n;
         o[4] = sqrt(res[1] / n);
