@@ -544,7 +544,7 @@ template hipError_t launch_finalize<double>(const RunDesc<double> *, int, int, i
 size_t ctx_footprint(const mhd_params &p)
 {
     const size_t n = (size_t)p.nx * p.ny * p.nz;
-    const size_t fb = align_up(n * (size_t)p.precision, 256);
+    const size_t fb = field_spacing(n, p.precision);
     const int nt = run_ntiles(p, default_shape(p));
     return 14 * fb + (size_t)(nt + run_nb2(p, default_shape(p))) * DIAGW * 8 +
            (size_t)CHUNK * forcing_stride(p) * p.precision +
@@ -591,7 +591,7 @@ mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *
     c->ncell = (size_t)p->nx * p->ny * p->nz;
     c->stream = (hipStream_t)stream;
     c->fstride = forcing_stride(*p);
-    const size_t fb = align_up(c->ncell * (size_t)p->precision, 256);
+    const size_t fb = field_spacing(c->ncell, p->precision);
     bool aligned = true;
     if (bufs) {
         for (int s = 0; s < 2; s++)

@@ -25,6 +25,17 @@ constexpr int CHUNK = 512;
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Bytes from one field array to the next in a context's state block.  Fields of at
+// least 4 MiB are spaced by their size plus 260.25 KiB: at the plain size (a power of
+// two on 2^n grids) the reads of one cell from the fourteen arrays fall at addresses
+// that differ only in high bits, and the substeps of a 512^3 FP64 run measured 5-6 %
+// slower (FP32 about 1 %); pads of 128-768 KiB plus 4.25 KiB all did as well.
+inline size_t field_spacing(size_t ncell, int precision)
+{
+    const size_t fb = align_up(ncell * (size_t)precision, 256);
+    return fb >= ((size_t)4 << 20) ? fb + (256 + 4) * 1024 + 256 : fb;
+}
+
 mhd_status fail(mhd_status s, const std::string &msg);
 extern thread_local std::string g_err;
 
