@@ -214,6 +214,10 @@ mhd_status mhd_set_tile_shape(const mhd_params *p, int32_t i);
  * (chosen by the autotuner or the default table); writes into buf. */
 mhd_status mhd_tile_config(const mhd_params *p, char *buf, size_t len);
 
+/* Tile shape this context's launches use, in the same form (a context of a batch may
+ * differ from mhd_tile_config: see mhd_batch_create). */
+mhd_status mhd_ctx_tile_config(const mhd_ctx *ctx, char *buf, size_t len);
+
 /* Try every compiled tile shape on a scratch run of this size and precision, time
  * `reps` steps of each on the given stream, and keep the fastest for later
  * contexts of the same (grid, precision).  best_ms: time per step of the winner. */
@@ -223,7 +227,11 @@ mhd_status mhd_autotune(const mhd_params *p, int reps, void *hip_stream, double 
 
 /* A set of independent runs (any grid sizes, same or mixed precision) advanced
  * together: each substep of every run is one tile list, launched as one kernel per
- * (precision, tile shape) class.  Runs never wait on each other's data. */
+ * (precision, tile shape) class.  Runs never wait on each other's data.  Each run
+ * takes the tile shape it would take alone (so its state is bit for bit the same),
+ * except that when the runs of one precision bring at least 4096 work-groups per
+ * substep with the large-grid tile, grids of at most 64^3 take that tile too
+ * (their state then matches the run alone to the parity bar, not bit for bit). */
 mhd_status mhd_batch_create(const mhd_params *runs, int32_t n, void *hip_stream,
                             mhd_batch **out);
 mhd_status mhd_batch_destroy(mhd_batch *b);

@@ -102,6 +102,7 @@ _SIGS = {
     "mhd_tile_shape_name": (C.c_int, [C.c_int32, C.c_char_p, C.c_size_t]),
     "mhd_set_tile_shape": (C.c_int, [C.POINTER(mhd_params), C.c_int32]),
     "mhd_tile_config": (C.c_int, [C.POINTER(mhd_params), C.c_char_p, C.c_size_t]),
+    "mhd_ctx_tile_config": (C.c_int, [_P, C.c_char_p, C.c_size_t]),
     "mhd_autotune": (C.c_int, [C.POINTER(mhd_params), C.c_int, _P, C.POINTER(C.c_double)]),
     "mhd_batch_create": (C.c_int, [C.POINTER(mhd_params), C.c_int32, _P, C.POINTER(_P)]),
     "mhd_batch_destroy": (C.c_int, [_P]),
@@ -359,6 +360,12 @@ def mhd_set_tile_shape(p: mhd_params, i: int) -> None:
 def mhd_tile_config(p: mhd_params) -> str:
     buf = C.create_string_buffer(64)
     _check(lib.mhd_tile_config(C.byref(p), buf, 64))
+    return buf.value.decode()
+
+
+def mhd_ctx_tile_config(ctx: int) -> str:
+    buf = C.create_string_buffer(64)
+    _check(lib.mhd_ctx_tile_config(ctx, buf, 64))
     return buf.value.decode()
 
 

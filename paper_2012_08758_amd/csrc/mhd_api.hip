@@ -103,7 +103,7 @@ bool shape_fits(const mhd_params &p, int shape)
     return p.nx >= s.tx + 8 && p.ny >= s.ty + 6 && p.nz >= s.tz + 6;
 }
 
-int default_shape(const mhd_params &p, bool aligned)
+int default_shape(const mhd_params &p, bool aligned, bool filled)
 {
     int want = -1;
     {
@@ -113,9 +113,9 @@ int default_shape(const mhd_params &p, bool aligned)
     }
     if (want < 0) {
         // measured at 512^3: 16x8x8/2 is the fastest FP64 ring shape, 32x4x8/2 the
-        // fastest FP32 one; small grids want the small tile (more work-groups)
+        // fastest FP32 one; a small grid alone wants the small tile (more work-groups)
         const double n = (double)p.nx * p.ny * p.nz;
-        want = n <= 64.0 * 64 * 64 ? 8 : (p.precision == MHD_FP64 ? 9 : 11);
+        want = (n <= 64.0 * 64 * 64 && !filled) ? 8 : (p.precision == MHD_FP64 ? 9 : 11);
     }
     while (!shape_eligible(p, want, aligned)) want = shape_fallback(want);
     return want;
@@ -1140,13 +1140,26 @@ mhd_status mhd_growth_rate(const mhd_diag *d, int64_t n, int64_t i0, int64_t i1,
     return MHD_OK;
 }
 
+static void shape_name(int shape, char *buf, size_t len)
+{
+    const Shape &s = SHAPES[shape];
+    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.march ? "+march" : (s.pipe ? "+ring" : ""));
+}
+
 mhd_status mhd_tile_config(const mhd_params *p, char *buf, size_t len)
 {
     mhd_status st = check_params(p);
     if (st != MHD_OK) return st;
     if (!buf || len == 0) return fail(MHD_E_INVALID, "buffer is NULL");
-    const Shape &s = SHAPES[default_shape(*p)];
-    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.march ? "+march" : (s.pipe ? "+ring" : ""));
+    shape_name(default_shape(*p), buf, len);
+    return MHD_OK;
+}
+
+mhd_status mhd_ctx_tile_config(const mhd_ctx *c, char *buf, size_t len)
+{
+    if (!c) return fail(MHD_E_INVALID, "ctx is NULL");
+    if (!buf || len == 0) return fail(MHD_E_INVALID, "buffer is NULL");
+    shape_name(c->shape, buf, len);
     return MHD_OK;
 }
 

@@ -87,7 +87,9 @@ namespace mhd {
 
 mhd_status check_params(const mhd_params *p);
 mhd_status check_forcing(const mhd_forcing &f);
-int default_shape(const mhd_params &p, bool aligned = true);
+// filled: other runs of a batch fill the chip, so a small grid need not take the
+// small tile that gives it enough work-groups alone
+int default_shape(const mhd_params &p, bool aligned = true, bool filled = false);
 bool shape_eligible(const mhd_params &p, int shape, bool aligned);
 bool shape_fits(const mhd_params &p, int shape);
 int forcing_stride(const mhd_params &p);

@@ -452,6 +452,50 @@ def test_batched_ensemble_equals_runs_alone(mhd, use_graph):
         mhd.mhd_batch_destroy(b)
 
 
+def test_a_batch_that_fills_the_chip_gives_small_grids_the_large_tile(mhd):
+    """16 FP32 runs of 64^3 bring 4096 work-groups per substep with the large-grid tile:
+    the batch gives them that tile instead of the small one they take alone, and each
+    run still matches the oracle step by step at the FP32 bar.  Two such runs do not
+    fill the chip and keep the tile they take alone."""
+    rps = [mi.RunParams(64, 64, 64, nu=2e-3, eta=2e-3, dt=1e-3, precision=4) for _ in range(16)]
+    alone_cfg = mhd.mhd_tile_config(mhd.params_from(rps[0]))
+    b2 = mhd.mhd_batch_create([mhd.params_from(rp) for rp in rps[:2]])
+    try:
+        assert mhd.mhd_ctx_tile_config(mhd.mhd_batch_ctx(b2, 0)) == alone_cfg
+    finally:
+        mhd.mhd_batch_destroy(b2)
+    states = [mi.noise_state(rp, 80 + i, 0.1, 0.1, 0.1, dtype=np.float32) for i, rp in enumerate(rps)]
+    scheds = [mi.forcing_schedule(90 + i, 2, 3.0, 0.05, float(i % 2)) for i in range(len(rps))]
+    outs = []
+    b = mhd.mhd_batch_create([mhd.params_from(rp) for rp in rps])
+    try:
+        ctxs = [mhd.mhd_batch_ctx(b, i) for i in range(len(rps))]
+        cfg = mhd.mhd_ctx_tile_config(ctxs[0])
+        print(f"alone {alone_cfg}, in the batch {cfg}", flush=True)
+        assert cfg == "32x4x8/2+ring" and cfg != alone_cfg
+        for c, st, r in zip(ctxs, states, scheds):
+            for f in range(7):
+                mhd.mhd_set_field(c, f, np.ascontiguousarray(st[f]))
+            mhd.mhd_set_forcing(c, r)
+        for _ in range(2):
+            mhd.mhd_batch_run(b, 1, False)
+            step = []
+            for i in (0, 7, 15):
+                got = np.empty_like(states[i])
+                for f in range(7):
+                    mhd.mhd_get_field(ctxs[i], f, got[f])
+                step.append(got)
+            outs.append(step)
+    finally:
+        mhd.mhd_batch_destroy(b)
+    for j, i in enumerate((0, 7, 15)):
+        cur = states[i].astype(np.float64)
+        for k in range(2):
+            want, ts = oracle.step(cur, rps[i], [scheds[i][k]])
+            check_step(outs[k][j], want, ts[0], rps[i], f"batch run {i} step {k + 1}")
+            cur = outs[k][j].astype(np.float64)
+
+
 def test_server_continuous_batching_equals_alone(mhd):
     """Runs that arrive while others are in flight are admitted by footprint, advance
     together, and finish with exactly the state they reach alone."""
