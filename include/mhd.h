@@ -230,8 +230,9 @@ mhd_status mhd_autotune(const mhd_params *p, int reps, void *hip_stream, double 
  * (precision, tile shape) class.  Runs never wait on each other's data.  Each run
  * takes the tile shape it would take alone (so its state is bit for bit the same),
  * except that when the runs of one precision bring at least 4096 work-groups per
- * substep with the large-grid tile, grids of at most 64^3 take that tile too
- * (their state then matches the run alone to the parity bar, not bit for bit). */
+ * substep with the large-grid tile, grids of at most 64^3 take that tile too, unless
+ * mhd_autotune pinned a shape for them (their state then matches the run alone to
+ * the parity bar, not bit for bit). */
 mhd_status mhd_batch_create(const mhd_params *runs, int32_t n, void *hip_stream,
                             mhd_batch **out);
 mhd_status mhd_batch_destroy(mhd_batch *b);
