@@ -150,3 +150,25 @@ def test_channel_growth_rate_is_half_the_log_slope():
         mhd.mhd_channel_growth_rate(t[:1], np.ones(1))
     with pytest.raises(mhd.MhdError):
         mhd.mhd_channel_growth_rate(t, np.zeros(50))
+
+
+def test_null_handles_are_rejected():
+    """Every entry point that takes a context, batch or server handle refuses NULL with
+    MHD_E_INVALID (no device work: these fail before any HIP call)."""
+    mhd = _mhd()
+    lib = mhd.lib
+    buf = C.create_string_buffer(64)
+    d, s, i32 = C.c_double(), C.c_int64(), C.c_int32()
+    calls = {
+        "mhd_step": lambda: lib.mhd_step(None, 1),
+        "mhd_reduce": lambda: lib.mhd_reduce(None),
+        "mhd_sync": lambda: lib.mhd_sync(None),
+        "mhd_get_time": lambda: lib.mhd_get_time(None, C.byref(s), C.byref(d)),
+        "mhd_ctx_tile_config": lambda: lib.mhd_ctx_tile_config(None, buf, 64),
+        "mhd_spectrum": lambda: lib.mhd_spectrum(None, None, 0, C.byref(i32), C.byref(d)),
+        "mhd_init_seed": lambda: lib.mhd_init_seed(None, 1, 1e-5),
+        "mhd_clear_forcing": lambda: lib.mhd_clear_forcing(None),
+        "mhd_batch_run": lambda: lib.mhd_batch_run(None, 1, 1),
+    }
+    for name, call in calls.items():
+        assert call() == mhd.MHD_E_INVALID, name
