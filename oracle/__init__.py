@@ -67,8 +67,6 @@ def lib():
                                      C.POINTER(C.c_int64), dp]
         L.ora_terms_cells.argtypes = [dp, C.POINTER(_Params), C.POINTER(_Forcing), C.c_int64,
                                       C.POINTER(C.c_int64), dp]
-        L.ora_rhs_patch.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                                    C.POINTER(_Params), C.POINTER(_Forcing), dp]
         L.ora_deriv.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                 C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, dp]
         L.ora_forcing_field.argtypes = [C.POINTER(_Params), C.POINTER(_Forcing), dp]
@@ -159,16 +157,6 @@ def terms_cells(state, p, rec, cells):
     return out
 
 
-def rhs_patch(patch, origin, p, rec):
-    """RHS on a non-periodic patch (7, mz, my, mx); cells within 3 of a face are NaN."""
-    pt = np.ascontiguousarray(patch, dtype=np.float64)
-    _, mz, my, mx = pt.shape
-    R = np.empty_like(pt)
-    lib().ora_rhs_patch(_dp(pt), mx, my, mz, int(origin[0]), int(origin[1]), int(origin[2]),
-                        C.byref(_params(p)), _forcings([rec]), _dp(R))
-    return R
-
-
 def deriv(f, h, kind, a, b=0, wrap=True):
     """One derivative operator on a scalar array (nz, ny, nx): kind 1 d_a, 2 d_a^2, 3 d_a d_b."""
     g = np.ascontiguousarray(f, dtype=np.float64)
@@ -211,7 +199,7 @@ def growth_rate(t, brms, i0=0, i1=None) -> float:
 
 
 def magnetic_spectrum(state, p):
-    """Shell spectrum E_B(k) of the discrete magnetic field (Section 6.2 power spectra).
+    """Shell spectrum E_B(k) of the discrete magnetic field (Section 5.3, power spectra).
 
     Follows the definition: B = curl A with the sixth-order first derivative (plus
     B_ext), its discrete Fourier transform B_hat(k) = sum_x B(x) exp(-i k.x) (a

@@ -448,31 +448,6 @@ int ora_terms_cells(const double *state, const ora_params *p, const ora_forcing 
     return 0;
 }
 
-/* Right-hand side on a non-periodic patch of size (mx, my, mz) whose local
- * (0,0,0) is global index (ox, oy, oz); only cells at least 3 from every face are
- * evaluated (the others are set to NaN).  Grid spacing comes from p. */
-int ora_rhs_patch(const double *patch, int mx, int my, int mz, int ox, int oy, int oz,
-                  const ora_params *p, const ora_forcing *fr, double *R)
-{
-    size_t n = (size_t)mx * my * mz;
-    view v;
-    for (int f = 0; f < NF; f++) v.f[f] = patch + f * n;
-    v.mx = mx; v.my = my; v.mz = mz; v.wrap = 0; v.ox = ox; v.oy = oy; v.oz = oz;
-    for (int l = 0; l < mz; l++)
-        for (int j = 0; j < my; j++)
-            for (int i = 0; i < mx; i++) {
-                size_t idx = (size_t)i + (size_t)mx * ((size_t)j + (size_t)my * l);
-                if (i < 3 || j < 3 || l < 3 || i >= mx - 3 || j >= my - 3 || l >= mz - 3) {
-                    for (int f = 0; f < NF; f++) R[f * n + idx] = NAN;
-                    continue;
-                }
-                double r[NF];
-                rhs_cell(&v, p, fr, i, j, l, r, NULL);
-                for (int f = 0; f < NF; f++) R[f * n + idx] = r[f];
-            }
-    return 0;
-}
-
 /* Single derivative operators on one scalar array of dims (nx, ny, nz), spacing
  * (hx, hy, hz).  kind 1: d_a, kind 2: d_a d_a, kind 3: d_a d_b.  wrap = 1:
  * periodic; wrap = 0: cells within 3 of a face are set to NaN. */

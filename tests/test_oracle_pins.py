@@ -648,3 +648,208 @@ def test_channel_growth_rate_of_a_decaying_beltrami_field_equals_the_rms_rate():
     lam = math.log(abs(rk3_poly(-p.eta * k2eff(k, h) ** 2 * p.dt))) / p.dt
     assert abs(oracle.spectral_growth_rate(ts, ek) - lam) < 1e-10
     assert abs(oracle.growth_rate(ts, br) - lam) < 1e-10
+
+
+# ------------------------------------------------------------------ tolerance scale T_f
+#
+# The parity bar divides by max(||f||, dt * T_f) with T_f = sum over the field's
+# right-hand-side terms of max |term| (largest over the step's substeps).  These pins
+# fix every term slot on states where each term has a closed form in the modified
+# wavenumbers of the stencils, so that a term filed under the wrong index, counted
+# twice or left out changes a slot that is checked here.
+#
+# Slots per field: ln rho: |u.grad ln rho|, sum_a |d_a u_a|, |upwinding|;
+# u_c: |advection|, |pressure|, |Lorentz|, |nu lap u|, |nu/3 grad div u|,
+#      |2 nu S.grad ln rho|, |forcing|;  A_c: |(u x B)_c|, |eta lap A_c|.
+
+def _terms_all(st, p, rec=NOFORCE):
+    cells = np.arange(p.ncell, dtype=np.int64)
+    t = oracle.terms_cells(st, p, rec, cells)  # (ncell, 7, 7)
+    return t.reshape(p.nz, p.ny, p.nx, 7, 7)
+
+
+def _close(got, want, scale):
+    assert np.max(np.abs(got - want)) <= 1e-12 * scale, (np.max(np.abs(got - want)), scale)
+
+
+def test_term_slots_shear_lorentz_and_induction_closed_forms():
+    # ln rho = eps sin(a x), u = (U sin(b y), 0, W), A = (0, 0, al sin(c x))
+    p = _p(16, 16, 8, nu=0.03, eta=0.02, cs=1.3)
+    X, Y, _ = _coords(p)
+    h = TWO_PI / 16
+    eps, U, W, al = 0.3, 0.7, 0.4, 0.9
+    a, b, c = 2, 3, 1
+    st = np.zeros((7, p.nz, p.ny, p.nx))
+    st[0] = eps * np.sin(a * X)
+    st[1] = U * np.sin(b * Y)
+    st[3] = W
+    st[6] = al * np.sin(c * X)
+    t = _terms_all(st, p)
+    a1, b1, c1 = keff(a, h), keff(b, h), keff(c, h)
+    b2, c2 = k2eff(b, h) ** 2, k2eff(c, h) ** 2
+    dlx = eps * a1 * np.cos(a * X)            # d_x ln rho (the only gradient component)
+    dyux = U * b1 * np.cos(b * Y)             # d_y u_x (the only velocity gradient)
+    By = -al * c1 * np.cos(c * X)             # B = curl A = (0, B_y, 0)
+    jz = al * c2 * np.sin(c * X)              # j = grad div A - lap A = (0, 0, j_z)
+    zero = np.zeros_like(X)
+    want = {
+        (0, 0): np.abs(U * np.sin(b * Y) * dlx), (0, 1): zero, (0, 2): zero,
+        (1, 0): zero, (1, 1): p.cs ** 2 * np.abs(dlx),
+        (1, 2): np.abs(np.exp(-st[0]) * (-jz * By)), (1, 3): p.nu * b2 * np.abs(U * np.sin(b * Y)),
+        (1, 4): zero, (1, 5): zero, (1, 6): zero,
+        (2, 0): zero, (2, 1): zero, (2, 2): zero, (2, 3): zero, (2, 4): zero,
+        # 2 nu S_yx d_x ln rho, S_yx = (d_y u_x)/2
+        (2, 5): p.nu * np.abs(dyux * dlx), (2, 6): zero,
+        (3, 0): zero, (3, 1): zero, (3, 2): zero, (3, 3): zero, (3, 4): zero, (3, 5): zero,
+        (3, 6): zero,
+        (4, 0): np.abs(W * By), (4, 1): zero,                 # (u x B)_x = -u_z B_y
+        (5, 0): zero, (5, 1): zero,
+        (6, 0): np.abs(U * np.sin(b * Y) * By),               # (u x B)_z = u_x B_y
+        (6, 1): p.eta * c2 * np.abs(al * np.sin(c * X)),
+    }
+    for (f, s), w in want.items():
+        _close(t[..., f, s], w, 1.0)
+    # slots that no field has are left at zero
+    assert np.all(t[..., 0, 3:] == 0.0) and np.all(t[..., 4:, 2:] == 0.0)
+
+
+def test_term_slots_compressive_flow_closed_forms():
+    # u = (U sin(a x), 0, 0), ln rho = eps sin(b y): advection, grad div, the trace part
+    # of the strain and the divergence slot of ln rho
+    p = _p(16, 16, 8, nu=0.05, cs=0.8)
+    X, Y, _ = _coords(p)
+    h = TWO_PI / 16
+    U, eps, a, b = 0.6, 0.25, 2, 1
+    st = np.zeros((7, p.nz, p.ny, p.nx))
+    st[1] = U * np.sin(a * X)
+    st[0] = eps * np.sin(b * Y)
+    t = _terms_all(st, p)
+    a1, a2, b1 = keff(a, h), k2eff(a, h) ** 2, keff(b, h)
+    dxux = U * a1 * np.cos(a * X)
+    dly = eps * b1 * np.cos(b * Y)
+    zero = np.zeros_like(X)
+    _close(t[..., 0, 0], zero, 1.0)                                   # u_x d_x ln rho = 0
+    _close(t[..., 0, 1], np.abs(dxux), 1.0)
+    _close(t[..., 1, 0], np.abs(U * np.sin(a * X) * dxux), 1.0)       # u_x d_x u_x
+    _close(t[..., 1, 3], p.nu * a2 * np.abs(U * np.sin(a * X)), 1.0)
+    _close(t[..., 1, 4], p.nu / 3.0 * a2 * np.abs(U * np.sin(a * X)), 1.0)
+    _close(t[..., 1, 5], zero, 1.0)                                   # S_xy = 0, d_x ln rho = 0
+    _close(t[..., 2, 1], p.cs ** 2 * np.abs(dly), 1.0)
+    # 2 nu S_yy d_y ln rho with the traceless S_yy = -(div u)/3
+    _close(t[..., 2, 5], 2.0 * p.nu / 3.0 * np.abs(dxux * dly), 1.0)
+    for f, s in [(1, 1), (1, 2), (2, 0), (2, 3), (2, 4), (3, 5)]:
+        _close(t[..., f, s], zero, 1.0)
+
+
+def test_term_slots_upwinding_and_forcing():
+    # uniform u_x = U under ln rho = eps sin(a x): the upwinding slot is the sixth-difference
+    # symbol; with a forcing record, the forcing slot is |f| of the forcing field
+    p = _p(16, 8, 8, upwind=0.7)
+    X, _, _ = _coords(p)
+    h = TWO_PI / 16
+    U, eps, a = 0.5, 0.2, 3
+    st = np.zeros((7, p.nz, p.ny, p.nx))
+    st[1] = U
+    st[0] = eps * np.sin(a * X)
+    rec = mi.forcing_schedule(4, 1, 3.0, 0.05, 0.5)[0]
+    t = _terms_all(st, p, rec)
+    sym = 64.0 * math.sin(a * h / 2) ** 6
+    _close(t[..., 0, 2], p.upwind * U * eps * sym * np.abs(np.sin(a * X)) / (60.0 * h), 1.0)
+    F = oracle.forcing_field(p, rec)
+    for c in range(3):
+        _close(t[..., 1 + c, 6], np.abs(F[c]), max(1.0, np.max(np.abs(F))))
+
+
+def test_rhs_termmax_is_the_largest_term_over_cells():
+    p = _p(12, 10, 8, nu=0.02, eta=0.01)
+    st = mi.smooth_state(p, 3, kmax=2, amp_lnrho=0.2, amp_u=0.4, amp_a=0.4, nmodes=3)
+    rec = mi.forcing_schedule(2, 1, 3.0, 0.05, 1.0)[0]
+    _, tm = oracle.rhs(st, p, rec)
+    t = _terms_all(st, p, rec)
+    assert np.array_equal(tm, t.reshape(-1, 7, 7).max(axis=0))
+
+
+def test_step_tscale_of_a_shear_wave():
+    # u = (0, U sin kx, 0) stays a shear wave: only nu lap u_y is non-zero, largest in
+    # substep 1 (the amplitude decays), and its maximum over the grid is nu k2^2 U
+    p = _p(32, 4, 4, nu=0.2, eta=0.1, dt=0.01)
+    X, _, _ = _coords(p)
+    U, k = 0.3, 2  # the grid holds x = pi/4 where sin(2x) = 1
+    st = np.zeros((7, p.nz, p.ny, p.nx))
+    st[2] = U * np.sin(k * X)
+    _, ts = oracle.step(st, p, mi.no_forcing(1))
+    want = np.array([0.0, 0.0, p.nu * k2eff(k, TWO_PI / 32) ** 2 * U, 0.0, 0.0, 0.0, 0.0])
+    assert np.all(ts[0][want == 0.0] == 0.0), ts
+    assert abs(ts[0][2] - want[2]) <= 1e-13 * want[2], ts
+
+
+def test_step_tscale_of_a_beltrami_field():
+    # A = (sin kz, cos kz, 0)/k, u = 0: A decays by diffusion only (T = eta k2^2 / k for
+    # A_x and A_y, 0 for A_z); j x B vanishes up to roundoff, so the u and ln rho scales
+    # are roundoff-sized
+    p = _p(8, 8, 32, eta=0.1, nu=0.05, dt=0.01)
+    _, _, Z = _coords(p)
+    k = 2
+    st = np.zeros((7, p.nz, p.ny, p.nx))
+    st[4] = np.sin(k * Z) / k
+    st[5] = np.cos(k * Z) / k
+    _, ts = oracle.step(st, p, mi.no_forcing(1))
+    w = p.eta * k2eff(k, TWO_PI / 32) ** 2 / k
+    assert abs(ts[0][4] - w) <= 1e-13 * w and abs(ts[0][5] - w) <= 1e-13 * w, ts
+    assert ts[0][6] == 0.0
+    assert np.all(ts[0][:4] < 1e-12 * w), ts
+
+
+def test_step_tscale_sums_the_terms_of_a_field():
+    # sound wave ln rho = eps sin(kx), u = 0: in substep 1 only the pressure acts on u_x;
+    # later substeps add u_x-driven terms of order dt, so T(u_x) = cs^2 eps keff (1 + O(dt))
+    # and T(ln rho) = sum of |u.grad ln rho| and |d_x u_x|, both of order dt
+    p = _p(32, 4, 4, nu=0.01, dt=1e-4)
+    X, _, _ = _coords(p)
+    eps, k = 0.01, 3
+    st = np.zeros((7, p.nz, p.ny, p.nx))
+    st[0] = eps * np.sin(k * X)
+    _, ts = oracle.step(st, p, mi.no_forcing(1))
+    h = TWO_PI / 32
+    pres = p.cs ** 2 * eps * keff(k, h)
+    assert abs(ts[0][1] - pres) <= 2e-3 * pres, ts
+    # ln rho: after substep 2, u_x ~ (beta1 + ...) dt * pres; d_x u_x ~ keff u_x
+    assert 0.0 < ts[0][0] < 2.0 * p.dt * pres * keff(k, h), ts
+    assert np.all(ts[0][2:] == 0.0), ts
+
+
+def test_tolerance_error_uses_the_larger_of_field_norm_and_term_floor():
+    ora = np.zeros((7, 2, 2, 2))
+    ora[1, 0, 0, 0] = 2.0          # ||u_x|| = 2
+    gpu = ora.copy()
+    gpu[1, 1, 1, 1] += 1e-6        # error 1e-6 in u_x
+    gpu[0, 0, 0, 1] += 3e-9        # error 3e-9 in ln rho, whose norm is 0
+    ts = np.array([5.0, 1e5, 0, 0, 0, 0, 0])
+    e, plain = oracle.tolerance_error(gpu, ora, ts, 1e-3)
+    assert abs(e[1] - 1e-6 / max(2.0, 1e-3 * 1e5)) < 1e-20   # the term floor 100 wins
+    assert abs(e[0] - 3e-9 / (1e-3 * 5.0)) < 1e-20            # norm 0: the floor alone
+    assert abs(plain[1] - 5e-7) < 1e-20 and plain[0] == 3e-9
+    assert np.all(e[2:] == 0.0)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_term_slots_compression_along_each_axis(axis):
+    # u_a = V sin(k x_a) along one axis a: every slot that holds d_a u_a or d_a d_a u_a
+    p = _p(16, 12, 20, nu=0.04)
+    C3 = _coords(p)
+    n = (p.nx, p.ny, p.nz)[axis]
+    h = TWO_PI / n
+    V, k = 0.8, 2
+    st = np.zeros((7, p.nz, p.ny, p.nx))
+    s = np.sin(k * C3[axis])
+    st[1 + axis] = V * s
+    t = _terms_all(st, p)
+    k1, k2 = keff(k, h), k2eff(k, h) ** 2
+    dadua = V * k1 * np.cos(k * C3[axis])
+    _close(t[..., 0, 1], np.abs(dadua), 1.0)
+    _close(t[..., 1 + axis, 0], np.abs(V * s * dadua), 1.0)
+    _close(t[..., 1 + axis, 3], p.nu * k2 * np.abs(V * s), 1.0)
+    _close(t[..., 1 + axis, 4], p.nu / 3.0 * k2 * np.abs(V * s), 1.0)
+    for b in range(3):
+        if b != axis:
+            assert np.all(t[..., 1 + b, :6] == 0.0)
