@@ -91,7 +91,7 @@ typedef struct {
     double t;
     double em, ek, urms, brms, umax, lnrho_mean;
     double b_mean[3];
-    double nonfinite;
+    int64_t nonfinite;       /* cells holding a NaN or Inf in any field */
 } mhd_diag;
 
 typedef struct mhd_ctx mhd_ctx;
@@ -168,7 +168,7 @@ mhd_status mhd_field_ptr(mhd_ctx *ctx, int field, void **dptr);
 mhd_status mhd_growth_rate(const mhd_diag *d, int64_t n, int64_t i0, int64_t i1,
                            double *lambda);
 
-/* Magnetic power spectrum of the current state (Section 6.2).  B = curl A with the
+/* Magnetic power spectrum of the current state (Section 5.3).  B = curl A with the
  * sixth-order first derivative (plus b_ext); with B_hat(k) = sum_x B(x) exp(-i k.x),
  * shell s (s = 0 .. nshell-1) collects the wavevectors with s - 1/2 <= |k|/dk < s + 1/2,
  * dk = 2 pi / max(lx, ly, lz), and out[s] = V / (2 dk Ncell^2) * sum_{k in s} |B_hat(k)|^2,

@@ -48,7 +48,7 @@ class mhd_forcing(C.Structure):
 class mhd_diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("t", C.c_double), ("em", C.c_double), ("ek", C.c_double),
                 ("urms", C.c_double), ("brms", C.c_double), ("umax", C.c_double),
-                ("lnrho_mean", C.c_double), ("b_mean", C.c_double * 3), ("nonfinite", C.c_double)]
+                ("lnrho_mean", C.c_double), ("b_mean", C.c_double * 3), ("nonfinite", C.c_int64)]
 
 
 class mhd_run_info(C.Structure):

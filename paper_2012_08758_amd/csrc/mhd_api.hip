@@ -729,7 +729,7 @@ mhd_status ctx_drain(mhd_ctx *c)
         d.b_mean[0] = r[8];
         d.b_mean[1] = r[9];
         d.b_mean[2] = r[10];
-        d.nonfinite = r[11];
+        d.nonfinite = (int64_t)r[11];  /* an exact count, carried as a double on the device */
         c->host_diag.push_back(d);
     }
     c->rcount = 0;

@@ -699,8 +699,10 @@ struct Interior {
             const G<T> *base = f == 0 ? s0 : (f == 1 ? s1 : (f == 2 ? s2 : s3));
             const int c0 = (qb - f * IV + lane) * EPL;
             const int x = c0 % TX, y = (c0 / TX) % TY, z = c0 / (TX * TY);
-            int gx = x0s + x;
-            gx -= gx >= nx ? nx : 0;
+            // x0s + x < 2 nx for the tile's own cells, but a tile wider than the grid
+            // (TX > nx) reaches further: wrap fully, so that every lane's 16-byte vector
+            // lies inside the field (x0s, x and nx are multiples of EPL)
+            const int gx = (x0s + x) % nx;
             const int gy = min(y0 + y, ny - 1), gz = min(z0 + z, nz - 1);
             const uint32_t off = (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz);
             __builtin_amdgcn_global_load_lds((gconst_void_t *)(base + off), (lds_void_t *)(area + qb * EPL), 16, 0, 0);
@@ -726,9 +728,7 @@ struct ForcingSlots {
         if (j < HV) {
             p = fs + j * EPL;
         } else if ((j -= HV) < TX) {
-            int gx = x0s + j;
-            gx -= gx >= nx ? nx : 0;
-            p = Ex + EPL * gx;
+            p = Ex + EPL * ((x0s + j) % nx);  // full wrap: TX may exceed nx
         } else if ((j -= TX) < TY) {
             p = Ey + EPL * min(y0 + j, ny - 1);
         } else if ((j -= TY) < TZ) {

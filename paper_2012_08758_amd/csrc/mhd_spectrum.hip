@@ -1,4 +1,4 @@
-// Magnetic power spectrum E_B(k) of a run's current state (Section 6.2), on the device.
+// Magnetic power spectrum E_B(k) of a run's current state (Section 5.3), on the device.
 //
 // B = curl A with the sixth-order first derivative is a circulant operator, so its
 // discrete Fourier transform is B_hat(k) = i kappa(k) x A_hat(k), kappa_a the modified

@@ -25,7 +25,7 @@ import time
 import numpy as np
 
 PAPER_LAMBDA = {1.0: 1.73e-2, 0.0: -1.35e-2}  # Tables 1 and 2, N = 64, eta = 5e-3
-CHANNELS = (1, 5, 9)  # the spectral channels followed in Section 6.2
+CHANNELS = (1, 5, 9)  # the spectral channels followed in Section 5.3
 
 
 def run(mhd, sigma: float, tmax: float, dt: float, seed: int, n: int = 64, eta: float = 5e-3, f0: float = 0.08):

@@ -80,25 +80,32 @@ def oracle_per_step(st, rp, recs):
 
 @pytest.mark.parametrize("prec", [8, 4])
 def test_config1_32cubed_every_step(mhd, prec):
-    """32^3, nu = eta = 5e-3, non-helical forcing kf = 3, f0 = 0.02, A noise 1e-5, 20 steps."""
+    """32^3, nu = eta = 5e-3, non-helical forcing kf = 3, f0 = 0.02, A noise 1e-5, 20 steps.
+
+    Every step is checked from a shared state: the oracle advances the GPU's own state
+    of the previous step (FP32 values promoted exactly to FP64) with the same record.
+    The diagnostic record of step n is the FP64 reduction of that step's input state,
+    so it must equal the oracle's reduction of the same state to 1e-12 at either
+    precision (FP32 states are reduced in FP64, with an FP64 curl, on the device)."""
     rp = mi.RunParams(32, 32, 32, nu=5e-3, eta=5e-3, dt=1e-3, precision=prec)
     st = mi.ic_seed_noise(rp, 0, 1e-5, dtype=_dtype(prec))
     recs = mi.forcing_schedule(0, 20, 3.0, 0.02, 0.0)
     got, diag = gpu_run(mhd, rp, st, recs, per_step=True)
-    want, scales = oracle_per_step(st, rp, recs)
+    inputs = [st.astype(np.float64)] + [g.astype(np.float64) for g in got]
     for n in range(20):
-        check_step(got[n], want[n], scales[n], rp, f"cfg1 fp{8 * prec} step {n + 1}")
+        want, ts = oracle.step(inputs[n], rp, [recs[n]])
+        check_step(got[n], want, ts[0], rp, f"cfg1 fp{8 * prec} step {n + 1}")
+    # the whole 20-step trajectory stays within the per-step bar of the oracle's own one
+    traj, tsc = oracle_per_step(st, rp, recs)
+    check_step(got[-1], traj[-1], tsc[-1], rp, f"cfg1 fp{8 * prec} trajectory")
     # diagnostics of the input state of every step, and of the final state
     assert len(diag) == 21
-    # (step 0 is the shared input; later FP32 states are the GPU's own FP32 trajectory,
-    # compared with the oracle's FP64 one at the FP32 bar)
-    states = [st.astype(np.float64)] + want
     for n, rec in enumerate(diag):
-        ref = oracle.diag(states[n], rp)
-        tol = 1e-12 if (prec == 8 or n == 0) else 1e-5
+        ref = oracle.diag(inputs[n], rp)
         assert rec["step"] == n and abs(rec["t"] - n * rp.dt) < 1e-15
         for k in ("em", "ek", "urms", "brms", "umax"):
-            assert abs(rec[k] - ref[k]) <= tol * abs(ref[k]) + 1e-300, (n, k, rec[k], ref[k])
+            assert abs(rec[k] - ref[k]) <= 1e-12 * abs(ref[k]) + 1e-300, (n, k, rec[k], ref[k])
+        assert rec["nonfinite"] == 0
 
 
 @pytest.mark.parametrize("shape", range(14))
@@ -121,6 +128,24 @@ def test_tile_shapes_fp32(mhd, shape):
     want, scales = oracle_per_step(st, rp, recs)
     for n in range(2):
         check_step(got[n], want[n], scales[n], rp, f"fp32 shape {shape} step {n + 1}")
+
+
+@pytest.mark.parametrize("prec", [8, 4])
+@pytest.mark.parametrize("grid", [(8, 8, 8), (12, 8, 8)])
+@pytest.mark.parametrize("shape", [7, 10, 11])
+def test_wide_ring_tiles_on_narrow_grids(mhd, shape, grid, prec):
+    """Ring tiles 32 cells wide on grids of 8 and 12 points in x: one tile spans the
+    periodic x axis several times, so the copies of the s-2 state and of the forcing
+    slots wrap x more than once."""
+    rp = mi.RunParams(*grid, nu=4e-3, eta=3e-3, dt=1e-3, precision=prec)
+    st = mi.noise_state(rp, 200 + shape, 0.2, 0.2, 0.2, dtype=_dtype(prec))
+    recs = mi.forcing_schedule(9, 2, 3.0, 0.05, 1.0)
+    got, _ = gpu_run(mhd, rp, st, recs, per_step=True, shape=shape)
+    cur = st.astype(np.float64)
+    for n in range(2):
+        want, ts = oracle.step(cur, rp, [recs[n]])
+        check_step(got[n], want, ts[0], rp, f"shape {shape} grid {grid} fp{8 * prec} step {n + 1}")
+        cur = got[n].astype(np.float64)
 
 
 @pytest.mark.parametrize("prec", [8, 4])
@@ -493,6 +518,45 @@ def test_a_batch_that_fills_the_chip_gives_small_grids_the_large_tile(mhd):
         for k in range(2):
             want, ts = oracle.step(cur, rps[i], [scheds[i][k]])
             check_step(outs[k][j], want, ts[0], rps[i], f"batch run {i} step {k + 1}")
+            cur = outs[k][j].astype(np.float64)
+
+
+def test_a_filled_batch_gives_an_8cubed_run_the_large_tile(mhd):
+    """An FP32 batch whose large run brings more than 4096 work-groups per substep hands
+    the 32-wide ring tile to an 8^3 run in the same batch; that run (and a 12 x 8 x 8 one)
+    still meets the FP32 bar against the oracle at every step."""
+    rps = [mi.RunParams(256, 256, 128, nu=1e-3, eta=1e-3, precision=4),
+           mi.RunParams(8, 8, 8, nu=4e-3, eta=3e-3, precision=4),
+           mi.RunParams(12, 8, 8, nu=4e-3, eta=3e-3, precision=4)]
+    states = [mi.noise_state(rp, 300 + i, 0.1, 0.1, 0.1, dtype=np.float32) for i, rp in enumerate(rps)]
+    scheds = [mi.forcing_schedule(310 + i, 2, 3.0, 0.05, 1.0) for i in range(len(rps))]
+    outs = []
+    b = mhd.mhd_batch_create([mhd.params_from(rp) for rp in rps])
+    try:
+        ctxs = [mhd.mhd_batch_ctx(b, i) for i in range(len(rps))]
+        cfgs = [mhd.mhd_ctx_tile_config(c) for c in ctxs]
+        print("tiles in the batch:", cfgs, flush=True)
+        assert cfgs[1] == cfgs[2] == "32x4x8/2+ring"
+        for c, st, r in zip(ctxs, states, scheds):
+            for f in range(7):
+                mhd.mhd_set_field(c, f, np.ascontiguousarray(st[f]))
+            mhd.mhd_set_forcing(c, r)
+        for _ in range(2):
+            mhd.mhd_batch_run(b, 1, False)
+            step = []
+            for i in (1, 2):
+                got = np.empty_like(states[i])
+                for f in range(7):
+                    mhd.mhd_get_field(ctxs[i], f, got[f])
+                step.append(got)
+            outs.append(step)
+    finally:
+        mhd.mhd_batch_destroy(b)
+    for j, i in enumerate((1, 2)):
+        cur = states[i].astype(np.float64)
+        for k in range(2):
+            want, ts = oracle.step(cur, rps[i], [scheds[i][k]])
+            check_step(outs[k][j], want, ts[0], rps[i], f"narrow batch run {i} step {k + 1}")
             cur = outs[k][j].astype(np.float64)
 
 
