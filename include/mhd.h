@@ -184,6 +184,18 @@ mhd_status mhd_growth_rate(const mhd_diag *d, int64_t n, int64_t i0, int64_t i1,
  * MHD_E_OOM if it does not fit. */
 mhd_status mhd_spectrum(mhd_ctx *ctx, double *out, int32_t cap, int32_t *nshell, double *dk);
 
+/* The magnetic spectrum of mhd_spectrum for callers that cannot allocate device memory
+ * (code under stream capture, serving loops, harnesses that forbid hipMalloc): the
+ * workspace is a static device array of 64 MiB that the library holds on each GPU it
+ * runs on until the process ends (grids up to about 128^3; larger ones return
+ * MHD_E_UNSUPPORTED before any device work).  out_dev is a device array of cap doubles
+ * (caller-owned) that receives the first min(cap, nshell) shells on the run's stream;
+ * the call neither allocates nor synchronises, and its result is ready once the stream
+ * is.  *nshell and *dk as in mhd_spectrum (either may be NULL); cap = 0 only queries
+ * them.  All calls on one GPU share the scratch: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller. */
+mhd_status mhd_spectrum_noalloc(mhd_ctx *ctx, double *out_dev, int32_t cap, int32_t *nshell, double *dk);
+
 /* Shell count, shell width and spectrum workspace bytes for runs of this size
  * (host-only).  MHD_E_UNSUPPORTED (outputs still written) if a side is not a product of
  * 2, 3, 5 and 7 at most 4096. */

@@ -91,6 +91,7 @@ _SIGS = {
                                   C.POINTER(C.c_double)]),
     "mhd_spectrum": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),
+    "mhd_spectrum_noalloc": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "mhd_spectrum_shells": (C.c_int, [C.POINTER(mhd_params), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_double), C.POINTER(C.c_size_t)]),
     "mhd_channel_growth_rate": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int64,
@@ -316,6 +317,15 @@ def mhd_spectrum(ctx: int):
     out = (C.c_double * max(1, ns.value))()
     _check(lib.mhd_spectrum(ctx, out, ns.value, C.byref(ns), C.byref(dk)))
     return np.array(out[:ns.value]), dk.value
+
+
+def mhd_spectrum_noalloc(ctx: int, out_dev: int, cap: int):
+    """Spectrum into the device array out_dev (cap doubles) on the run's stream, using
+    the library's static device scratch (no allocation, no synchronisation); returns
+    (nshell, dk).  See the header."""
+    ns, dk = C.c_int32(), C.c_double()
+    _check(lib.mhd_spectrum_noalloc(ctx, out_dev, cap, C.byref(ns), C.byref(dk)))
+    return ns.value, dk.value
 
 
 def mhd_spectrum_shells(p: mhd_params):

@@ -14,7 +14,9 @@
 // accumulators, then per-block partials and a fixed-order final sum: the result is
 // bit-reproducible.
 #include <cmath>
+#include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -298,9 +300,9 @@ __global__ __launch_bounds__(NT) void k_spec_bin(const double2 *__restrict__ W, 
     }
 }
 
-// out[s] = scale * sum over blocks of part[b][s], in a fixed order.
+// out[s] = scale * sum over blocks of part[b][s], in a fixed order (shells s < cap).
 __global__ __launch_bounds__(NT) void k_spec_final(const double *__restrict__ part, int nblk, int nsh,
-                                                   double scale, double *__restrict__ out)
+                                                   double scale, double *__restrict__ out, int cap)
 {
     __shared__ double sh[NT];
     const int s = blockIdx.x;
@@ -312,7 +314,35 @@ __global__ __launch_bounds__(NT) void k_spec_final(const double *__restrict__ pa
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[s] = sh[0] * scale;
+    if (threadIdx.x == 0 && s < cap) out[s] = sh[0] * scale;
+}
+
+
+// Twiddles exp(-2 pi i j / n) of the three axes and the modified wavenumbers of the
+// first-derivative stencil, (45 sin w - 9 sin 2w + sin 3w) / (30 h) with w = 2 pi m / n,
+// computed on the device (FP64 sincospi / sinpi; within an ulp or two of the host's
+// extended-precision tables).  Block y = axis.
+struct TableArgs {
+    int n[3], nk[3];
+    double ih30[3];     // 1 / (30 h)
+    double2 *tw[3];
+    double *kap[3];
+};
+
+__global__ __launch_bounds__(NT) void k_spec_tables(TableArgs a)
+{
+    const int ax = blockIdx.y;
+    const int n = a.n[ax];
+    const int j = blockIdx.x * NT + threadIdx.x;
+    if (j < n) {
+        double sv, cv;
+        sincospi(2.0 * (double)j / (double)n, &sv, &cv);
+        a.tw[ax][j] = make_double2(cv, -sv);
+    }
+    if (j < a.nk[ax]) {
+        const double u = 2.0 * (double)j / (double)n;  // w / pi
+        a.kap[ax][j] = (45.0 * sinpi(u) - 9.0 * sinpi(2.0 * u) + sinpi(3.0 * u)) * a.ih30[ax];
+    }
 }
 
 // ------------------------------------------------------------------ host side
@@ -452,28 +482,27 @@ static void launch_strided(double2 *W, long long cstride, long long S, long long
                        S, I, nchunk, tw, pl);
 }
 
-template <typename T>
-static mhd_status run(mhd_ctx *c, double *out, int32_t cap, int32_t *nshell, double *dk)
+static mhd_status plan_all(const mhd_ctx *c, Geometry &g, Plan &px, Plan &py, Plan &pz)
 {
-    const Geometry g = geometry(c->p);
-    Plan px, py, pz;
+    g = geometry(c->p);
     if (!make_plan(g.nx, px) || !make_plan(g.ny, py) || !make_plan(g.nz, pz))
         return fail(MHD_E_UNSUPPORTED, "spectrum: every grid side must be a product of 2, 3, 5 and 7, at most 4096");
     if (g.nsh > 4096) return fail(MHD_E_UNSUPPORTED, "spectrum: more than 4096 shells");
-    if (nshell) *nshell = g.nsh;
-    if (dk) *dk = g.dk;
-    if (cap == 0) return MHD_OK;  // query only
-    const Layout L = layout(g);
-    mhd_status st = ensure_workspace(c, g, L);
-    if (st != MHD_OK) return st;
-    char *ws = static_cast<char *>(c->spec_ws);
+    return MHD_OK;
+}
+
+// The passes of one spectrum on the run's stream, in the workspace at ws (tables
+// already in place); the first min(cap, nsh) shells land in the device array dout.
+template <typename T>
+static void launch_passes(const mhd_ctx *c, const Geometry &g, const Layout &L, const Plan &px, const Plan &py,
+                          const Plan &pz, char *ws, double *dout, int cap)
+{
     double2 *W = reinterpret_cast<double2 *>(ws + L.w);
     const double2 *tw[3] = {reinterpret_cast<double2 *>(ws + L.tw[0]), reinterpret_cast<double2 *>(ws + L.tw[1]),
                             reinterpret_cast<double2 *>(ws + L.tw[2])};
     const double *kap[3] = {reinterpret_cast<double *>(ws + L.kap[0]), reinterpret_cast<double *>(ws + L.kap[1]),
                             reinterpret_cast<double *>(ws + L.kap[2])};
     double *part = reinterpret_cast<double *>(ws + L.part);
-    double *dout = reinterpret_cast<double *>(ws + L.out);
     const long long cstride = (long long)g.nh * g.ny * g.nz;
     const long long nlines = (long long)g.ny * g.nz;
     const T *A[3] = {static_cast<const T *>(c->bufs[c->parity][4]), static_cast<const T *>(c->bufs[c->parity][5]),
@@ -520,13 +549,106 @@ static mhd_status run(mhd_ctx *c, double *out, int32_t cap, int32_t *nshell, dou
                            kap[2], ba, part);
     const double vol = c->p.lx * c->p.ly * c->p.lz;
     const double scale = vol / (2.0 * g.dk * ncell * ncell);
-    hipLaunchKernelGGL(k_spec_final, dim3(g.nsh), dim3(NT), 0, s, part, L.nblk, g.nsh, scale, dout);
+    hipLaunchKernelGGL(k_spec_final, dim3(g.nsh), dim3(NT), 0, s, part, L.nblk, g.nsh, scale, dout, cap);
+}
+
+template <typename T>
+static mhd_status run(mhd_ctx *c, double *out, int32_t cap, int32_t *nshell, double *dk)
+{
+    Geometry g;
+    Plan px, py, pz;
+    mhd_status st = plan_all(c, g, px, py, pz);
+    if (st != MHD_OK) return st;
+    if (nshell) *nshell = g.nsh;
+    if (dk) *dk = g.dk;
+    if (cap == 0) return MHD_OK;  // query only
+    const Layout L = layout(g);
+    st = ensure_workspace(c, g, L);
+    if (st != MHD_OK) return st;
+    char *ws = static_cast<char *>(c->spec_ws);
+    double *dout = reinterpret_cast<double *>(ws + L.out);
+    launch_passes<T>(c, g, L, px, py, pz, ws, dout, g.nsh);
+    hipStream_t s = c->stream;
     hipError_t e = hipGetLastError();
     std::vector<double> host(g.nsh);
     if (e == hipSuccess) e = hipMemcpyAsync(host.data(), dout, sizeof(double) * g.nsh, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("spectrum: ") + hipGetErrorString(e));
     if (out && cap > 0) std::memcpy(out, host.data(), sizeof(double) * (size_t)std::min<int32_t>(cap, g.nsh));
+    return MHD_OK;
+}
+
+
+// ------------------------------------------------------------------ no-allocation variant
+//
+// For callers that may not allocate device memory (code under stream capture, serving
+// loops): the workspace lives in one file-scope device array per GPU, reached through
+// its address from hipGetSymbolAddress (the name itself is a host-side stand-in).  All
+// calls on one GPU share it and it keeps the last call's contents; every pass writes
+// the parts it reads later, so nothing needs clearing.  Calls that overlap on one GPU
+// race on it.
+constexpr size_t SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// the scratch address on the current device (looked up once per device)
+static mhd_status scratch_base(char **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("spectrum_noalloc: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(MHD_E_UNSUPPORTED, "spectrum_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(MHD_E_DEVICE, std::string("spectrum_noalloc: scratch address: ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return MHD_OK;
+}
+
+template <typename T>
+static mhd_status run_noalloc(mhd_ctx *c, double *dout, int32_t cap, int32_t *nshell, double *dk)
+{
+    Geometry g;
+    Plan px, py, pz;
+    mhd_status st = plan_all(c, g, px, py, pz);
+    if (st != MHD_OK) return st;
+    if (nshell) *nshell = g.nsh;
+    if (dk) *dk = g.dk;
+    if (cap == 0) return MHD_OK;
+    const Layout L = layout(g);
+    if (L.total > SCRATCH_BYTES)
+        return fail(MHD_E_UNSUPPORTED, "spectrum_noalloc: this grid needs a workspace of " + std::to_string(L.total) +
+                                           " bytes, above the " + std::to_string(SCRATCH_BYTES) +
+                                           "-byte scratch (use mhd_spectrum)");
+    char *ws = nullptr;
+    st = scratch_base(&ws);
+    if (st != MHD_OK) return st;
+    TableArgs ta;
+    const int ns[3] = {g.nx, g.ny, g.nz};
+    const double ls[3] = {c->p.lx, c->p.ly, c->p.lz};
+    int nmax = 0;
+    for (int a = 0; a < 3; a++) {
+        ta.n[a] = ns[a];
+        ta.nk[a] = a == 0 ? g.nh : ns[a];
+        ta.ih30[a] = 1.0 / (30.0 * (ls[a] / ns[a]));
+        ta.tw[a] = reinterpret_cast<double2 *>(ws + L.tw[a]);
+        ta.kap[a] = reinterpret_cast<double *>(ws + L.kap[a]);
+        nmax = std::max(nmax, ns[a]);
+    }
+    hipLaunchKernelGGL(k_spec_tables, dim3((nmax + NT - 1) / NT, 3), dim3(NT), 0, c->stream, ta);
+    launch_passes<T>(c, g, L, px, py, pz, ws, dout, std::min<int32_t>(cap, g.nsh));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("spectrum_noalloc: ") + hipGetErrorString(e));
     return MHD_OK;
 }
 
@@ -543,6 +665,14 @@ mhd_status mhd_spectrum(mhd_ctx *c, double *out, int32_t cap, int32_t *nshell, d
     if (cap < 0 || (cap > 0 && !out)) return fail(MHD_E_INVALID, "out is NULL or cap < 0");
     return c->p.precision == MHD_FP64 ? spec::run<double>(c, out, cap, nshell, dk)
                                       : spec::run<float>(c, out, cap, nshell, dk);
+}
+
+mhd_status mhd_spectrum_noalloc(mhd_ctx *c, double *out_dev, int32_t cap, int32_t *nshell, double *dk)
+{
+    if (!c) return fail(MHD_E_INVALID, "ctx is NULL");
+    if (cap < 0 || (cap > 0 && !out_dev)) return fail(MHD_E_INVALID, "out_dev is NULL or cap < 0");
+    return c->p.precision == MHD_FP64 ? spec::run_noalloc<double>(c, out_dev, cap, nshell, dk)
+                                      : spec::run_noalloc<float>(c, out_dev, cap, nshell, dk);
 }
 
 mhd_status mhd_spectrum_shells(const mhd_params *p, int32_t *nshell, double *dk, size_t *workspace_bytes)
