@@ -33,7 +33,8 @@ VALUES_PER_CELL_STEP = 14 + 21 + 21
 PAPER_NS_PER_POINT_STEP = 0.65
 
 
-KERNEL_SOURCES = ("paper_2012_08758_amd/csrc/mhd_device.h", "paper_2012_08758_amd/csrc/mhd_api.hip")
+KERNEL_SOURCES = ("paper_2012_08758_amd/csrc/mhd_device.h", "paper_2012_08758_amd/csrc/mhd_zmarch.h",
+                  "paper_2012_08758_amd/csrc/mhd_api.hip")
 
 
 def kernel_source_hash():
@@ -51,7 +52,7 @@ def stored_traffic(prec, n, tile):
     """HBM bytes per launch of the dominant kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size), or None when
     there is none for this workload or the kernel sources changed since it was taken."""
-    name = os.path.join(ROOT, "profiles", f"traffic_k_pipe_sub2_fp{8 * prec}_{n}cubed.txt")
+    name = os.path.join(ROOT, "profiles", f"traffic_{kernel_name(tile)}_sub2_fp{8 * prec}_{n}cubed.txt")
     if not os.path.exists(name):
         return None
     kv = {}
@@ -62,6 +63,17 @@ def stored_traffic(prec, n, tile):
     if kv.get("source_sha256") != kernel_source_hash() or kv.get("tile") != tile:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def kernel_name(tile):
+    """The substep kernel that runs a tile shape."""
+    if tile.endswith("+zm"):
+        return "k_zm"
+    if tile.endswith("+ring"):
+        return "k_pipe"
+    if tile.endswith("+march"):
+        return "k_march"
+    return "k_substep"
 
 
 def log(msg):
@@ -493,8 +505,7 @@ def main():
         "kernel_ms": r64["kernel_ms"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("k_pipe" if "ring" in r64["tile"] else "k_substep")
-                               + f" substep 2 (fused RHS + RK3 update), tile {r64['tile']}",
+                     "kernel": kernel_name(r64["tile"]) + f" substep 2 (fused RHS + RK3 update), tile {r64['tile']}",
                      "algorithmic_bytes_per_launch": r64["sub2_bytes"],
                      "launch_ms": r64["sub2_ms"],
                      "all_substeps_gbs": r64["substep_kernel_gbs"]},

@@ -3,6 +3,7 @@
 // The serving loop lives in mhd_server.hip.
 #include "mhd.h"
 #include "mhd_host.h"
+#include "mhd_zmarch.h"
 
 #include <algorithm>
 #include <chrono>
@@ -62,11 +63,14 @@ const Shape SHAPES[NSHAPES] = {
     // z-marching column kernel (ring per field in LDS): the tile divides the grid
     {16, 8, 4, 1, true, true},  // 12: FP32 only (the FP64 rings do not fit the LDS)
     {8, 8, 4, 1, true, true},   // 13
+    // z-marching kernel with register queues: nx % 32 == 0, ny % 8 == 0
+    {32, 8, 1, 1, false, false, true},  // 14
 };
 
 // the shape used when `shape` cannot run on a grid: march -> ring -> staged, same box
 int shape_fallback(int shape)
 {
+    if (shape == SHAPE_ZM) return 9;
     if (shape == 12) return 6;
     if (shape == 13) return 8;
     return SHAPES[shape].pipe ? shape - 6 : shape;
@@ -89,6 +93,7 @@ bool shape_eligible(const mhd_params &p, int shape, bool aligned)
 {
     if (shape < 0 || shape >= NSHAPES) return false;
     const Shape &s = SHAPES[shape];
+    if (s.zm) return aligned && p.nx % s.tx == 0 && p.ny % s.ty == 0 && p.nx % (16 / p.precision) == 0;
     if (!s.pipe) return true;
     const int epl = 16 / p.precision;
     if (!(aligned && p.nx % epl == 0)) return false;
@@ -113,9 +118,14 @@ int default_shape(const mhd_params &p, bool aligned, bool filled)
     }
     if (want < 0) {
         // measured at 512^3: 16x8x8/2 is the fastest FP64 ring shape, 32x4x8/2 the
-        // fastest FP32 one; a small grid alone wants the small tile (more work-groups)
+        // fastest FP32 one; a small grid alone wants the small tile (more work-groups).
+        // The z-marching kernel beats both once its columns and segments give at least
+        // 1024 work-groups (256^3: 2.64 against 3.59 ms per step in FP64, 1.65 against
+        // 1.81 in FP32; 512^3: 18.3 against 26.8 and 11.9 against 12.6); at 128^3 (128
+        // work-groups) the ring kernel is faster.
         const double n = (double)p.nx * p.ny * p.nz;
         want = (n <= 64.0 * 64 * 64 && !filled) ? 8 : (p.precision == MHD_FP64 ? 9 : 11);
+        if (shape_eligible(p, SHAPE_ZM, aligned) && run_ntiles(p, SHAPE_ZM) >= 1024) want = SHAPE_ZM;
     }
     while (!shape_eligible(p, want, aligned)) want = shape_fallback(want);
     return want;
@@ -327,9 +337,42 @@ int march_segment(const mhd_params &p, int shape)
     return p.nz / nseg;
 }
 
+// z-segments of a zm run: the columns times the segments make at least 2048 work-groups
+// (eight per CU at one per CU) while a segment keeps at least 64 planes, so that the six
+// planes of warm-up per segment cost little
+int zm_segment(const mhd_params &p)
+{
+    const Shape &s = SHAPES[SHAPE_ZM];
+    const long ncol = (long)(p.nx / s.tx) * (p.ny / s.ty);
+    int nseg = 1;
+    while (ncol * nseg < 2048 && p.nz / (2 * nseg) >= 64) nseg *= 2;
+    return (p.nz + nseg - 1) / nseg;
+}
+
 void run_tiles(const mhd_params &p, int shape, int run, std::vector<TileEnt> &out)
 {
     const Shape &s = SHAPES[shape];
+    if (s.zm) {
+        // columns in patches of 32 (the work-groups resident on one XCD at a time), so that
+        // neighbouring columns march side by side and share their x/y halo lines in L2
+        const int ntx = p.nx / s.tx, nty = p.ny / s.ty, seg = zm_segment(p), nseg = (p.nz + seg - 1) / seg;
+        int px = 1;
+        while (px * 2 <= ntx && px * px * 2 <= 32) px *= 2;
+        const int py = std::max(1, std::min(nty, 32 / px));
+        for (int sg = 0; sg < nseg; sg++)
+            for (int pY = 0; pY < nty; pY += py)
+                for (int pX = 0; pX < ntx; pX += px)
+                    for (int ty = pY; ty < std::min(nty, pY + py); ty++)
+                        for (int tx = pX; tx < std::min(ntx, pX + px); tx++) {
+                            TileEnt t;
+                            t.run = run;
+                            t.xy = (tx * s.tx) | ((ty * s.ty) << 16);
+                            t.z0 = sg * seg;
+                            t.tir = tx + ntx * (ty + nty * sg);
+                            out.push_back(t);
+                        }
+        return;
+    }
     if (s.march) {
         // columns in patches of ~32 (the work-groups resident on one XCD at a time), so
         // that columns marching side by side share their x/y halo lines in L2
@@ -382,6 +425,28 @@ void run_tiles(const mhd_params &p, int shape, int run, std::vector<TileEnt> &ou
 int x_shift(const mhd_params &p, int shape)
 {
     const Shape &s = SHAPES[shape];
+    if (s.zm) {  // the kernel wraps every copy fully: any offset that keeps vectors aligned
+        const int es = p.precision, epl = 16 / es, L = 128 / es;
+        const int ntx = p.nx / s.tx;
+        int best = 0;
+        long bestc = -1;
+        for (int xs = 0; xs < L; xs += epl) {
+            long cnt = 0;
+            for (int t = 0; t < ntx; t++) {
+                int prev = -1;
+                for (int e = t * s.tx + xs - 4; e < t * s.tx + xs + s.tx + 4; e++) {
+                    const int line = (((e % p.nx) + p.nx) % p.nx) / L;
+                    if (line != prev) cnt++;
+                    prev = line;
+                }
+            }
+            if (bestc < 0 || cnt < bestc) {
+                bestc = cnt;
+                best = xs;
+            }
+        }
+        return best;
+    }
     if (!s.pipe || !shape_fits(p, shape)) return 0;
     const int es = p.precision, epl = 16 / es, L = 128 / es;
     const int ntx = (p.nx + s.tx - 1) / s.tx;
@@ -409,6 +474,10 @@ int x_shift(const mhd_params &p, int shape)
 int run_ntiles(const mhd_params &p, int shape)
 {
     const Shape &s = SHAPES[shape];
+    if (s.zm) {
+        const int seg = zm_segment(p);
+        return (p.nx / s.tx) * (p.ny / s.ty) * ((p.nz + seg - 1) / seg);
+    }
     if (s.march) return (p.nx / s.tx) * (p.ny / s.ty) * (p.nz / march_segment(p, shape));
     return ((p.nx + s.tx - 1) / s.tx) * ((p.ny + s.ty - 1) / s.ty) * ((p.nz + s.tz - 1) / s.tz);
 }
@@ -500,11 +569,34 @@ static hipError_t launch_march(int kind, const RunDesc<T> *runs, const TileEnt *
     }
 }
 
+// z-marching kernel: FP64 at two waves per SIMD (256 registers, one 160 KB work-group
+// per CU), FP32 at four (128 registers, two 80 KB work-groups per CU) except substep 1,
+// whose FP64 diagnostics need more registers than that (two waves per SIMD)
+template <typename T>
+static hipError_t launch_zm(int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles, int step,
+                            hipStream_t st)
+{
+    constexpr int W = sizeof(T) == 8 ? 2 : 4;
+    constexpr int WD = 2;
+    const dim3 grid(ntiles), block(ZmCfg<T>::NT);
+    switch (kind) {
+    case 0: hipLaunchKernelGGL((k_zm<T, 0, true, true, WD>), grid, block, 0, st, runs, tiles, step); break;
+    case 1: hipLaunchKernelGGL((k_zm<T, 1, false, true, W>), grid, block, 0, st, runs, tiles, step); break;
+    case 2: hipLaunchKernelGGL((k_zm<T, 2, false, true, W>), grid, block, 0, st, runs, tiles, step); break;
+    case 4: hipLaunchKernelGGL((k_zm<T, 0, true, true, WD, true>), grid, block, 0, st, runs, tiles, step); break;
+    case 5: hipLaunchKernelGGL((k_zm<T, 1, false, true, W, true>), grid, block, 0, st, runs, tiles, step); break;
+    case 6: hipLaunchKernelGGL((k_zm<T, 2, false, true, W, true>), grid, block, 0, st, runs, tiles, step); break;
+    default: hipLaunchKernelGGL((k_zm<T, 0, true, false, WD>), grid, block, 0, st, runs, tiles, step); break;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles,
                           int step, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
+    if (shape == SHAPE_ZM) return launch_zm<T>(kind, runs, tiles, ntiles, step, st);
     switch (shape) {
     case 0: return launch_shape<T, 16, 8, 4, 1>(kind, runs, tiles, ntiles, step, st);
     case 1: return launch_shape<T, 32, 8, 4, 1>(kind, runs, tiles, ntiles, step, st);
@@ -619,7 +711,7 @@ mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *
     c->shape = shape >= 0 ? shape : default_shape(*p, aligned);
     c->fit = SHAPES[c->shape].pipe && shape_fits(*p, c->shape);
     c->xs = x_shift(*p, c->shape);
-    c->seg = march_segment(*p, c->shape);
+    c->seg = SHAPES[c->shape].zm ? zm_segment(*p) : march_segment(*p, c->shape);
     c->ntiles = run_ntiles(*p, c->shape);
     c->nb2 = run_nb2(*p, c->shape);
     mhd_status st = ctx_alloc_aux(c);
@@ -1143,7 +1235,10 @@ mhd_status mhd_growth_rate(const mhd_diag *d, int64_t n, int64_t i0, int64_t i1,
 static void shape_name(int shape, char *buf, size_t len)
 {
     const Shape &s = SHAPES[shape];
-    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.march ? "+march" : (s.pipe ? "+ring" : ""));
+    if (s.zm)
+        std::snprintf(buf, len, "%dx%d+zm", s.tx, s.ty);
+    else
+        std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.march ? "+march" : (s.pipe ? "+ring" : ""));
 }
 
 mhd_status mhd_tile_config(const mhd_params *p, char *buf, size_t len)
@@ -1176,8 +1271,7 @@ int32_t mhd_num_tile_shapes(void) { return NSHAPES; }
 mhd_status mhd_tile_shape_name(int32_t i, char *buf, size_t len)
 {
     if (i < 0 || i >= NSHAPES || !buf || len == 0) return fail(MHD_E_INVALID, "bad tile shape index or buffer");
-    const Shape &s = SHAPES[i];
-    std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.march ? "+march" : (s.pipe ? "+ring" : ""));
+    shape_name(i, buf, len);
     return MHD_OK;
 }
 

@@ -16,8 +16,10 @@ struct Shape {
     int tx, ty, tz, cz;
     bool pipe;   // true: direct-to-LDS ring kernel (k_pipe); false: register-staged kernel (k_substep)
     bool march;  // true: z-marching column kernel (k_march); tz is its slab depth
+    bool zm;     // true: z-marching kernel with register queues (k_zm); a tx x ty column tile
 };
-constexpr int NSHAPES = 14;
+constexpr int NSHAPES = 15;
+constexpr int SHAPE_ZM = 14;
 extern const Shape SHAPES[NSHAPES];
 
 // steps whose forcing blocks and diagnostic records are staged at once
@@ -118,6 +120,7 @@ hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int max_nb2, int s
 int run_nb2(const mhd_params &p, int shape);
 int x_shift(const mhd_params &p, int shape);
 int march_segment(const mhd_params &p, int shape);
+int zm_segment(const mhd_params &p);
 int shape_fallback(int shape);
 
 }  // namespace mhd

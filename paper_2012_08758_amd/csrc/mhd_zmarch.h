@@ -1,0 +1,763 @@
+// z-marching substep kernel with register queues ("zm").
+//
+// A work-group owns a 32 x 8 column tile of one run and walks a z-segment of it one
+// plane per step.  Each step brings one plane of each of the seven fields into LDS
+// (the tile plus a 3-cell x/y halo, x wrapped while copying) by direct-to-LDS loads,
+// two steps ahead of use, together with the s-2 state and the forcing phase of the
+// plane being finished.  The z direction never goes through LDS:
+//   * every thread keeps its own column's last six planes of its fields in registers
+//     (the newest plane is the seventh), so the z first and second derivatives at the
+//     plane three behind the newest come from registers;
+//   * the mixed x-z and y-z derivatives (sixth-order diagonal stencils) are sums over
+//     planes z +- s of x- (or y-) differences taken inside one plane, so each plane's
+//     differences are pushed, with their weights, into accumulators of the six output
+//     planes they reach (the +s part into plane z' - s, the -s part into z' + s);
+//   * the parts of a cell's right-hand side that only need its own plane (x/y
+//     derivatives and their products) are formed when the plane arrives and either
+//     added to the same pending accumulators or held three steps until the z parts
+//     are known.
+// Output (the RK3 update of the plane three behind the newest) then needs only
+// registers, so one plane of each field in LDS suffices.
+//
+// Threads 0..255 ("flow") carry ln rho and u of one column each, threads 256..511
+// ("field") carry A of the same columns; at each output plane they swap u and J x B
+// through LDS.  Register queues rotate with period six: the step loop is unrolled by
+// six so that every queue slot is a compile-time index.
+//
+// Needs nx % 32 == 0, ny % 8 == 0 and 16-byte aligned field arrays (checked on the host).
+#pragma once
+#include "mhd_device.h"
+
+namespace mhd {
+
+template <typename T>
+struct ZmCfg {
+    static constexpr int TX = 32, TY = 8, NC = TX * TY;   // columns of a tile
+    static constexpr int NT = 2 * NC;                      // flow + field threads
+    static constexpr int NW = NT / 64;                     // waves
+    static constexpr int EPL = 16 / (int)sizeof(T);        // values per 16-byte copy
+    static constexpr int XW = TX + 8, YW = TY + 6;         // plane box (x from x0-4)
+    static constexpr int PLE = XW * YW;                    // values per field plane
+    static constexpr int PV = PLE / EPL;                   // copies per field plane
+    // one step's planes: ln rho and u (read by flow threads) and A (field threads) land
+    // in separate regions, whole wave-copies each
+    static constexpr int NIF = (4 * PV + 63) / 64, NIA = (3 * PV + 63) / 64;
+    static constexpr int NLP = (NIF + NIA + NW - 1) / NW;  // plane copies per thread per step
+    static constexpr int FREG = NIF * 64 * EPL, AREG = NIA * 64 * EPL;  // values per slot
+    static constexpr int SV = NF * NC / EPL;               // copies of the s-2 state per step
+    static constexpr int NLS = (SV + 1 + NT - 1) / NT;     // ... plus the forcing z slot
+    static constexpr int SREG = NLS * NT * EPL;
+    static constexpr int D = 3;                            // slots: planes in flight + the one in use
+    static constexpr int FLOW = 0;                         // D flow regions
+    static constexpr int FIELD = FLOW + D * FREG;          // D field regions
+    static constexpr int S2 = FIELD + D * AREG;            // D s-2 regions (+ forcing z slot)
+    static constexpr int XU = S2 + D * SREG;               // exchange: u at the output plane [3][NC]
+    static constexpr int XJ = XU + 3 * NC;                 // exchange: J x B [3][NC]
+    static constexpr int FH = XJ + 3 * NC;                 // forcing head and the tile's x, y phase slots
+    static constexpr int NFH = FHEAD / EPL + TX + TY;
+    static constexpr int XF = FH + 64 * EPL;               // exchange: non-finite flag of A [NC]
+    static constexpr int LDS = XF + NC;
+    static_assert(PLE % EPL == 0 && XW % EPL == 0, "plane rows hold whole vectors");
+    static_assert(NFH <= 64, "forcing slots: one copy");
+    static_assert(NC % 64 == 0, "flow and field threads fill whole waves");
+    // every LDS read of a thread is an immediate offset (< 64 KiB) from one base
+    static_assert((D * FREG + 6 * XW) * (int)sizeof(T) < 65536 && (D * AREG + 6 * XW) * (int)sizeof(T) < 65536 &&
+                      (D * SREG) * (int)sizeof(T) < 65536,
+                  "regions within 16-bit LDS offsets");
+};
+
+// LDS pointers keep their address space through the asm barriers below (a generic
+// pointer there would turn every LDS read into a flat load)
+template <typename T>
+using LP = __attribute__((address_space(3))) T;
+
+// Folded stencil weights for the pushes of the mixed derivatives.
+template <typename T>
+struct ZmW {
+    T kxz[3], kyz[3];     // ihm_xz W2_s, ihm_yz W2_s (s = 1..3)
+};
+
+// wait until at most N vector-memory operations of this wave are outstanding
+// (a runtime choice among the counts that occur; the branch is wave-uniform)
+template <int NL, int NS>
+__device__ __forceinline__ void zm_wait(int key)
+{
+    __builtin_amdgcn_sched_barrier(0);
+    switch (key) {
+    case 0: __builtin_amdgcn_s_waitcnt(0x0070); break;  // vmcnt(0) lgkmcnt(0)
+    case 1: wait_vmcnt<NS>(); break;
+    case 2: wait_vmcnt<2 * NS>(); break;
+    case 3: wait_vmcnt<NL>(); break;
+    case 4: wait_vmcnt<NL + NS>(); break;
+    default: wait_vmcnt<NL + 2 * NS>(); break;
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Sums of the three symmetric pairs along one direction: p_s = f(+s) + f(-s) and the
+// differences d_s = f(+s) - f(-s), s = 1..3, at stride st from s[0].
+template <typename T>
+struct Pairs {
+    T c, p[3], d[3];
+    template <class PT>
+    __device__ __forceinline__ void load(const PT *s, int st)
+    {
+        c = s[0];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const T a = s[(k + 1) * st], b = s[-(k + 1) * st];
+            p[k] = a + b;
+            d[k] = a - b;
+        }
+    }
+    __device__ __forceinline__ T d1(T ih) const { return ih * (T(W1_1) * d[0] + T(W1_2) * d[1] + T(W1_3) * d[2]); }
+    __device__ __forceinline__ T d2(T ih2) const
+    {
+        return ih2 * (T(W2_0) * c + T(W2_1) * p[0] + T(W2_2) * p[1] + T(W2_3) * p[2]);
+    }
+    __device__ __forceinline__ T d6() const { return T(-20) * c + T(15) * p[0] + T(-6) * p[1] + p[2]; }
+};
+
+// d_x d_y from the two diagonals through s[0] (rows of stride sy)
+template <typename T, class PT>
+__device__ __forceinline__ T zm_dxy(const PT *s, int sy, T ihm)
+{
+    const int p = 1 + sy, q = 1 - sy;
+    return ihm * (T(W2_1) * ((s[p] + s[-p]) - (s[q] + s[-q])) + T(W2_2) * ((s[2 * p] + s[-2 * p]) - (s[2 * q] + s[-2 * q])) +
+                  T(W2_3) * ((s[3 * p] + s[-3 * p]) - (s[3 * q] + s[-3 * q])));
+}
+
+// z derivatives at the output plane from a register queue: q[(j + i) % 6] holds the
+// plane z' - 6 + i' ... see the callers; here v[0..6] = planes zo-3 .. zo+3.
+template <typename T>
+struct ZCol {
+    T v[7];
+    __device__ __forceinline__ T d1(T ih) const
+    {
+        return ih * (T(W1_1) * (v[4] - v[2]) + T(W1_2) * (v[5] - v[1]) + T(W1_3) * (v[6] - v[0]));
+    }
+    __device__ __forceinline__ T d2(T ih2) const
+    {
+        return ih2 * (T(W2_0) * v[3] + T(W2_1) * (v[4] + v[2]) + T(W2_2) * (v[5] + v[1]) + T(W2_3) * (v[6] + v[0]));
+    }
+    __device__ __forceinline__ double d1d(double ih) const
+    {
+        return ih * (W1_1 * ((double)v[4] - (double)v[2]) + W1_2 * ((double)v[5] - (double)v[1]) +
+                     W1_3 * ((double)v[6] - (double)v[0]));
+    }
+    __device__ __forceinline__ T d6() const
+    {
+        return T(-20) * v[3] + T(15) * (v[4] + v[2]) + T(-6) * (v[5] + v[1]) + (v[6] + v[0]);
+    }
+};
+
+// queue slot of the plane `back` steps behind the newest (0 = newest, held apart)
+template <int J, int BACK>
+struct QS {
+    static constexpr int v = ((J - BACK) % 6 + 6) % 6;
+};
+
+// the seven planes zo-3 .. zo+3 of one queue (newest plane in `now`)
+template <typename T, int J>
+__device__ __forceinline__ ZCol<T> zcol(const T (&q)[6], T now)
+{
+    ZCol<T> z;
+    z.v[0] = q[QS<J, 6>::v];
+    z.v[1] = q[QS<J, 5>::v];
+    z.v[2] = q[QS<J, 4>::v];
+    z.v[3] = q[QS<J, 3>::v];
+    z.v[4] = q[QS<J, 2>::v];
+    z.v[5] = q[QS<J, 1>::v];
+    z.v[6] = now;
+    return z;
+}
+
+// pending-accumulator slot of the output plane z' + off (z' = the newest plane)
+template <int J, int OFF>
+struct PS {
+    static constexpr int v = ((J + 3 + OFF) % 6 + 6) % 6;
+};
+
+// Push the mixed-derivative contributions q_s (s = 1..3) of the newest plane z': + into
+// the output plane z' - s, - into z' + s.  The s = 3 '+' part completes the current
+// output plane and is added before it is finished; the s = 3 '-' part starts the
+// accumulator of plane z' + 3, which takes over the slot the output just released, so
+// it is subtracted there; the caller cleared that slot after the output.
+template <typename T, int J>
+__device__ __forceinline__ void push3(T (&acc)[6], T q1, T q2, T q3)
+{
+    acc[PS<J, -1>::v] += q1;
+    acc[PS<J, 1>::v] -= q1;
+    acc[PS<J, -2>::v] += q2;
+    acc[PS<J, 2>::v] -= q2;
+    acc[PS<J, 3>::v] -= q3;
+}
+
+template <typename T, int SUB, bool DIAG, bool STORE, bool UPW>
+struct Zm {
+    using C = ZmCfg<T>;
+    static constexpr int NLS_E = STORE ? (SUB == 0 ? 1 : C::NLS) : 0;  // s-2 / forcing copies per step
+    static constexpr int NL = C::NLP + NLS_E;                         // copies per step per thread
+    static constexpr int NSF = STORE ? 4 : 0, NSA = STORE ? 3 : 0;     // stores per output (flow, field)
+    static constexpr int FZ = SUB == 0 ? 0 : C::SV * C::EPL;  // forcing z slot within an s-2 region
+    static_assert(NL + 2 * NSF < 64, "vmcnt is a 6-bit counter");
+};
+
+// substep constants of the update and the imposed field, read once and pinned in
+// scalar registers
+template <typename T>
+struct ZmK {
+    T bdt, brho, bext[3];
+    __device__ __forceinline__ void load(const Coef<T> &c, int sub)
+    {
+        bdt = c.bdt[sub];
+        brho = c.brho[sub];
+#pragma unroll
+        for (int a = 0; a < 3; a++) bext[a] = c.bext[a];
+        asm volatile("" : "+s"(bdt), "+s"(brho), "+s"(bext[0]), "+s"(bext[1]), "+s"(bext[2]));
+    }
+};
+
+// Register state of one thread.  A flow thread and a field thread of a column keep
+// the same layout (so that the kernel needs registers for one of them, not both):
+//   q:   last six planes of the thread's fields (ln rho, u_x, u_y, u_z / A_x, A_y, A_z),
+//        slot = step mod 6;
+//   acc: pending right-hand sides of u (flow) / current density (field) of the six
+//        output planes still open, slot = output step mod 6;
+//   del: per plane (slot = step mod 3) the in-plane parts held until its z parts exist:
+//        flow  g_x, g_y, d_x u_z, d_y u_z, div_xy u, R_lnrho part;
+//        field d_y A_z, -d_x A_z, d_x A_y - d_y A_x, eta (D2x + D2y) A_m.
+template <typename T>
+struct ZmState {
+    T q[4][6];
+    T acc[3][6];
+    T del[6][3];
+    T fpr, fpi;       // flow: forcing exp(i (k_x x + k_y y)) at the column
+    double dg[5];     // diagnostics: flow |u|^2, rho |u|^2, ln rho, max |u|^2, non-finite cells;
+                      //              field |B|^2, B_x, B_y, B_z
+    double bd[3][3];  // diagnostics of FP32 runs, field: the B parts of del in FP64
+};
+
+// first derivative in FP64 of FP32 values in LDS (diagnostics of FP32 runs)
+template <class PT>
+__device__ __forceinline__ double zm_d1d(const PT *s, int st, double ih)
+{
+    return ih * (W1_1 * ((double)s[st] - (double)s[-st]) + W1_2 * ((double)s[2 * st] - (double)s[-2 * st]) +
+                 W1_3 * ((double)s[3 * st] - (double)s[-3 * st]));
+}
+
+
+// One step of the march: wait for the newest plane z' (step k), request the plane two
+// steps ahead, finish the output plane z' - 3 (k >= 6), then fold plane z' into the
+// register queues and pending accumulators.  J = k mod 6 fixes every queue slot;
+// ROLE 0 is a flow thread, 1 a field thread.
+template <typename T, int SUB, bool DIAG, bool STORE, bool UPW, int ROLE, int J, class KR, class ISSUE>
+__device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, const KR &Kr, const ZmK<T> &Zk,
+                                        const DCoef &dc, const RunDesc<T> &r, LP<T> *pb0, LP<T> *sb0, LP<T> *xb0, int col,
+                                        uint64_t gcol, uint64_t plane_b, int zs, int out_set, T (&fa)[3], T (&fb)[3],
+                                        bool &fon, ISSUE &issue)
+{
+    using C = ZmCfg<T>;
+    using Z = Zm<T, SUB, DIAG, STORE, UPW>;
+    constexpr int NC = C::NC, PLE = C::PLE, XW = C::XW;
+    constexpr int JD = J % 3;                       // delayed-set slot of plane z'
+    constexpr int PO = PS<J, -3>::v;                // pending slot of the output plane (= J)
+    constexpr int PN = PS<J, 0>::v;                 // pending slot of plane z' itself
+    if (k >= K) return;
+    const int key = 3 * (k + 1 < K ? 1 : 0) + ((STORE && k - 1 >= 6) ? 1 : 0) + ((STORE && k - 2 >= 6) ? 1 : 0);
+    zm_wait<Z::NL, ROLE == 0 ? Z::NSF : Z::NSA>(key);
+    if (k + 2 < K) issue(k + 2, (J + 2) % 3);
+    // this thread's planes (pb0 points 3 rows and 3 columns before its column in slot 0
+    // of its role's region), s-2 values and exchange slots; the asm keeps the compiler
+    // from hoisting addresses derived from them out of the step loop
+    asm volatile("" : "+v"(pb0), "+v"(sb0), "+v"(xb0));
+    constexpr int CO = 3 * XW + 3;
+    const LP<T> *P = pb0 + JD * (ROLE == 0 ? C::FREG : C::AREG) + CO;  // P[f * PLE] = field f of the role at the column
+    const LP<T> *S2 = sb0 + JD * C::SREG;                               // S2[f * NC] = s-2 value of field f
+    const bool out = k >= 6;
+    const int zo = zs + k - 6;
+
+    if constexpr (STORE) {
+        if (k == 0) {  // forcing head and this column's x/y phase product (arrived with plane 0)
+            constexpr int HV = FHEAD / C::EPL;
+            const T *H = lds + C::FH;
+            fon = H[6] != T(0);
+#pragma unroll
+            for (int a = 0; a < 3; a++) { fa[a] = H[a]; fb[a] = H[3 + a]; }
+            const int cx = col % C::TX, cy = col / C::TX;
+            const T *ex = H + (HV + cx) * C::EPL, *ey = H + (HV + C::TX + cy) * C::EPL;
+            S.fpr = ex[0] * ey[0] - ex[1] * ey[1];
+            S.fpi = ex[0] * ey[1] + ex[1] * ey[0];
+        }
+    }
+
+    // ---------------------------------------------------------------- output plane
+    // the newest plane's centre values and the s = 3 differences that complete it
+    T now[4];
+    if constexpr (ROLE == 0) {
+        const LP<T> *L0 = P, *X = P + PLE, *Y = P + 2 * PLE, *W = P + 3 * PLE;
+        now[0] = L0[0];
+        now[1] = X[0];
+        now[2] = Y[0];
+        now[3] = W[0];
+        if constexpr (STORE) {
+            const T k3x = Kr.nu3 * Kr.ihm[1] * T(W2_3), k3y = Kr.nu3 * Kr.ihm[2] * T(W2_3);
+            S.acc[0][PO] += k3x * (W[3] - W[-3]);
+            S.acc[1][PO] += k3y * (W[3 * XW] - W[-3 * XW]);
+            S.acc[2][PO] += k3x * (X[3] - X[-3]) + k3y * (Y[3 * XW] - Y[-3 * XW]);
+        }
+    } else {
+        const LP<T> *AX = P, *AY = P + PLE, *AZ = P + 2 * PLE;
+        now[0] = AX[0];
+        now[1] = AY[0];
+        now[2] = AZ[0];
+        now[3] = T(0);
+        if constexpr (STORE) {
+            const T k3x = Kr.ihm[1] * T(W2_3), k3y = Kr.ihm[2] * T(W2_3);
+            S.acc[0][PO] += k3x * (AZ[3] - AZ[-3]);
+            S.acc[1][PO] += k3y * (AZ[3 * XW] - AZ[-3 * XW]);
+            S.acc[2][PO] += k3x * (AX[3] - AX[-3]) + k3y * (AY[3 * XW] - AY[-3 * XW]);
+        }
+    }
+
+    LP<T> *XU = xb0, *XJ = xb0 + (C::XJ - C::XU), *XF = xb0 + (C::XF - C::XU);  // [.. * NC] at the column
+    if (out) {
+        const T ihz = Kr.ih1[2], ih2z = Kr.ih2[2];
+        if constexpr (ROLE == 0) {
+            const ZCol<T> L = zcol<T, J>(S.q[0], now[0]), X = zcol<T, J>(S.q[1], now[1]);
+            const ZCol<T> Y = zcol<T, J>(S.q[2], now[2]), W = zcol<T, J>(S.q[3], now[3]);
+            const T l0 = L.v[3], ux = X.v[3], uy = Y.v[3], uz = W.v[3];
+            if constexpr (STORE) {
+                XU[0] = ux;
+                XU[NC] = uy;
+                XU[2 * NC] = uz;
+            }
+            if constexpr (DIAG) {
+                const double dx = (double)ux, dy = (double)uy, dz = (double)uz;
+                const double u2 = dx * dx + dy * dy + dz * dz;
+                S.dg[0] += u2;
+                S.dg[1] += exp((double)l0) * u2;
+                S.dg[2] += (double)l0;
+                S.dg[3] = fmax(S.dg[3], u2);
+            }
+            lds_barrier();  // u and J x B exchanged
+            if constexpr (DIAG) {
+                const bool bad = !(finite_v(l0) && finite_v(ux) && finite_v(uy) && finite_v(uz)) || XF[0] != T(0);
+                S.dg[4] += bad ? 1.0 : 0.0;
+            }
+            if constexpr (STORE) {
+                const T gz = L.d1(ihz), dzx = X.d1(ihz), dzy = Y.d1(ihz), dzz = W.d1(ihz);
+                const T gx = S.del[0][JD], gy = S.del[1][JD], dxz = S.del[2][JD], dyz = S.del[3][JD];
+                const T divxy = S.del[4][JD], pl = S.del[5][JD];
+                const T nu = Kr.nu, n23 = Kr.nu2_3;
+                const T rinv = exp(-l0);
+                const T jbx = XJ[0], jby = XJ[NC], jbz = XJ[2 * NC];
+                T R[4];
+                R[0] = pl - uz * gz - dzz;
+                if constexpr (UPW) R[0] += Kr.upw[2] * fabs(uz) * L.d6();
+                R[1] = S.acc[0][PO] + nu * X.d2(ih2z) - uz * dzx + nu * (dzx * gz + dxz * gz) - n23 * dzz * gx +
+                       rinv * jbx;
+                R[2] = S.acc[1][PO] + nu * Y.d2(ih2z) - uz * dzy + nu * (dzy * gz + dyz * gz) - n23 * dzz * gy +
+                       rinv * jby;
+                R[3] = S.acc[2][PO] + (nu + Kr.nu3) * W.d2(ih2z) - uz * dzz +
+                       nu * (T(2) * dzz * gz + dzx * gx + dzy * gy) - n23 * (divxy + dzz) * gz - Kr.cs2 * gz +
+                       rinv * jbz;
+                if (fon) {
+                    const T *Ez = lds + C::S2 + JD * C::SREG + Z::FZ;
+                    const T cr = S.fpr * Ez[0] - S.fpi * Ez[1], ci = S.fpr * Ez[1] + S.fpi * Ez[0];
+#pragma unroll
+                    for (int a = 0; a < 3; a++) R[1 + a] += fa[a] * cr + fb[a] * ci;
+                }
+                const T bdt = Zk.bdt, brho = Zk.brho;
+                const T v[4] = {l0, ux, uy, uz};
+                const uint64_t g = gcol + (uint64_t)zo * (plane_b / sizeof(T));
+#pragma unroll
+                for (int f = 0; f < 4; f++) {
+                    T o;
+                    if constexpr (SUB == 0) {
+                        o = v[f] + bdt * R[f];
+                    } else {
+                        const T old = S2[f * NC];
+                        o = v[f] + brho * (v[f] - old) + bdt * R[f];
+                    }
+                    ((G<T> *)r.buf[out_set][f])[g] = o;
+                }
+            }
+        } else {
+            const ZCol<T> AX = zcol<T, J>(S.q[0], now[0]), AY = zcol<T, J>(S.q[1], now[1]);
+            const ZCol<T> AZ = zcol<T, J>(S.q[2], now[2]);
+            const T dzax = AX.d1(ihz), dzay = AY.d1(ihz);
+            const T bx = Zk.bext[0] + S.del[0][JD] - dzay, by = Zk.bext[1] + dzax + S.del[1][JD];
+            const T bz = Zk.bext[2] + S.del[2][JD];
+            T jx = T(0), jy = T(0), jz = T(0);
+            if constexpr (STORE) {
+                jx = S.acc[0][PO] - AX.d2(ih2z);
+                jy = S.acc[1][PO] - AY.d2(ih2z);
+                jz = S.acc[2][PO];
+                XJ[0] = jy * bz - jz * by;
+                XJ[NC] = jz * bx - jx * bz;
+                XJ[2 * NC] = jx * by - jy * bx;
+            }
+            if constexpr (DIAG) {
+                double Bx, By, Bz;
+                if constexpr (sizeof(T) == 8) {
+                    Bx = (double)bx;
+                    By = (double)by;
+                    Bz = (double)bz;
+                } else {
+                    Bx = dc.bext[0] + S.bd[0][JD] - AY.d1d(dc.ih1[2]);
+                    By = dc.bext[1] + AX.d1d(dc.ih1[2]) + S.bd[1][JD];
+                    Bz = dc.bext[2] + S.bd[2][JD];
+                }
+                S.dg[0] += Bx * Bx + By * By + Bz * Bz;
+                S.dg[1] += Bx;
+                S.dg[2] += By;
+                S.dg[3] += Bz;
+                XF[0] = (finite_v(AX.v[3]) && finite_v(AY.v[3]) && finite_v(AZ.v[3])) ? T(0) : T(1);
+            }
+            lds_barrier();  // u and J x B exchanged
+            if constexpr (STORE) {
+                const T ux = XU[0], uy = XU[NC], uz = XU[2 * NC];
+                const T eta = Kr.eta;
+                T R[3];
+                R[0] = S.del[3][JD] + eta * AX.d2(ih2z) + (uy * bz - uz * by);
+                R[1] = S.del[4][JD] + eta * AY.d2(ih2z) + (uz * bx - ux * bz);
+                R[2] = S.del[5][JD] + eta * AZ.d2(ih2z) + (ux * by - uy * bx);
+                const T bdt = Zk.bdt, brho = Zk.brho;
+                const uint64_t g = gcol + (uint64_t)zo * (plane_b / sizeof(T));
+#pragma unroll
+                for (int m = 0; m < 3; m++) {
+                    const T vv = m == 0 ? AX.v[3] : (m == 1 ? AY.v[3] : AZ.v[3]);
+                    T o;
+                    if constexpr (SUB == 0) {
+                        o = vv + bdt * R[m];
+                    } else {
+                        const T old = S2[(4 + m) * NC];
+                        o = vv + brho * (vv - old) + bdt * R[m];
+                    }
+                    ((G<T> *)r.buf[out_set][4 + m])[g] = o;
+                }
+            }
+        }
+    }
+
+    // ---------------------------------------------------------------- fold in plane z'
+    // The output plane's slots are free now: they start the accumulators of plane z' + 3.
+    if constexpr (STORE) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) S.acc[m][PO] = T(0);
+    }
+    // Field by field, so that few values are live at once: each field's x/y pairs give
+    // its in-plane derivatives, which go straight into the accumulators, and its x- or
+    // y-differences, pushed as mixed x-z / y-z derivatives into the planes z' +- s.
+    if constexpr (ROLE == 0) {
+        const LP<T> *L0 = P, *X = P + PLE, *Y = P + 2 * PLE, *W = P + 3 * PLE;
+        if constexpr (STORE) {
+            const T ihx = Kr.ih1[0], ihy = Kr.ih1[1], i2x = Kr.ih2[0], i2y = Kr.ih2[1];
+            const T nu = Kr.nu, nu3 = Kr.nu3, n23 = Kr.nu2_3;
+            const T kx = nu3 * Kr.ihm[1], ky = nu3 * Kr.ihm[2];
+            const T ux = now[1], uy = now[2];
+            T gx, gy, pl;
+            {
+                Pairs<T> lx, ly;
+                lx.load(L0, 1);
+                ly.load(L0, XW);
+                gx = lx.d1(ihx);
+                gy = ly.d1(ihy);
+                pl = -(ux * gx + uy * gy);
+                if constexpr (UPW) pl += Kr.upw[0] * fabs(ux) * lx.d6() + Kr.upw[1] * fabs(uy) * ly.d6();
+            }
+            // u_x: R_x (viscous, advection, strain), R_y (grad div), R_z (mixed push)
+            T dxx, dyx;
+            {
+                Pairs<T> a, b;
+                a.load(X, 1);
+                b.load(X, XW);
+                dxx = a.d1(ihx);
+                dyx = b.d1(ihy);
+                const T d2xx = a.d2(i2x), d2yx = b.d2(i2y);
+                S.acc[0][PN] += nu * (d2xx + d2yx) + nu3 * d2xx - (ux * dxx + uy * dyx) + nu * (T(2) * dxx * gx + dyx * gy) -
+                                Kr.cs2 * gx;
+                S.acc[1][PN] += nu3 * zm_dxy(X, XW, Kr.ihm[0]);
+                push3<T, J>(S.acc[2], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
+            }
+            // u_y
+            T dyy;
+            {
+                Pairs<T> a, b;
+                a.load(Y, 1);
+                b.load(Y, XW);
+                const T dxy = a.d1(ihx);
+                dyy = b.d1(ihy);
+                const T d2xy = a.d2(i2x), d2yy = b.d2(i2y);
+                S.acc[1][PN] += nu * (d2xy + d2yy) + nu3 * d2yy - (ux * dxy + uy * dyy) + nu * (dxy * gx + T(2) * dyy * gy) +
+                                nu * dyx * gx - Kr.cs2 * gy;
+                S.acc[0][PN] += nu * dxy * gy + nu3 * zm_dxy(Y, XW, Kr.ihm[0]);
+                push3<T, J>(S.acc[2], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
+            }
+            const T divxy = dxx + dyy;
+            S.acc[0][PN] -= n23 * divxy * gx;
+            S.acc[1][PN] -= n23 * divxy * gy;
+            pl -= divxy;
+            // u_z
+            {
+                Pairs<T> a, b;
+                a.load(W, 1);
+                b.load(W, XW);
+                const T dxz = a.d1(ihx), dyz = b.d1(ihy);
+                S.acc[2][PN] += nu * (a.d2(i2x) + b.d2(i2y)) - (ux * dxz + uy * dyz) + nu * (dxz * gx + dyz * gy);
+                push3<T, J>(S.acc[0], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
+                push3<T, J>(S.acc[1], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
+                S.del[2][JD] = dxz;
+                S.del[3][JD] = dyz;
+            }
+            S.del[0][JD] = gx;
+            S.del[1][JD] = gy;
+            S.del[4][JD] = divxy;
+            S.del[5][JD] = pl;
+        }
+#pragma unroll
+        for (int f = 0; f < 4; f++) S.q[f][J] = now[f];
+    } else {
+        const LP<T> *AX = P, *AY = P + PLE, *AZ = P + 2 * PLE;
+        const T ihx = Kr.ih1[0], ihy = Kr.ih1[1];
+        if constexpr (STORE) {
+            const T i2x = Kr.ih2[0], i2y = Kr.ih2[1], eta = Kr.eta;
+            const T kx = Kr.ihm[1], ky = Kr.ihm[2];
+            T dyax;
+            {  // A_x: j_x -= D2y A_x, j_y += D_xy A_x, j_z += D_xz A_x (push), B_z -= d_y A_x
+                Pairs<T> a, b;
+                a.load(AX, 1);
+                b.load(AX, XW);
+                const T d2x = a.d2(i2x), d2y = b.d2(i2y);
+                dyax = b.d1(ihy);
+                S.acc[0][PN] -= d2y;
+                S.acc[1][PN] += zm_dxy(AX, XW, Kr.ihm[0]);
+                S.del[3][JD] = eta * (d2x + d2y);
+                push3<T, J>(S.acc[2], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
+            }
+            {  // A_y: j_y -= D2x A_y, j_x += D_xy A_y, j_z += D_yz A_y (push), B_z += d_x A_y
+                Pairs<T> a, b;
+                a.load(AY, 1);
+                b.load(AY, XW);
+                const T d2x = a.d2(i2x), d2y = b.d2(i2y);
+                S.del[2][JD] = a.d1(ihx) - dyax;
+                S.acc[1][PN] -= d2x;
+                S.acc[0][PN] += zm_dxy(AY, XW, Kr.ihm[0]);
+                S.del[4][JD] = eta * (d2x + d2y);
+                push3<T, J>(S.acc[2], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
+            }
+            {  // A_z: j_z -= D2x A_z + D2y A_z, j_x += D_xz A_z, j_y += D_yz A_z (pushes), B_x, B_y
+                Pairs<T> a, b;
+                a.load(AZ, 1);
+                b.load(AZ, XW);
+                const T d2x = a.d2(i2x), d2y = b.d2(i2y);
+                S.acc[2][PN] -= d2x + d2y;
+                S.del[0][JD] = b.d1(ihy);
+                S.del[1][JD] = -a.d1(ihx);
+                S.del[5][JD] = eta * (d2x + d2y);
+                push3<T, J>(S.acc[0], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
+                push3<T, J>(S.acc[1], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
+            }
+        } else {
+            // diagnostics only: the B parts of this plane
+            Pairs<T> ay, bx_, cx_, cy_;
+            ay.load(AX, XW);
+            bx_.load(AY, 1);
+            cx_.load(AZ, 1);
+            cy_.load(AZ, XW);
+            S.del[0][JD] = cy_.d1(ihy);
+            S.del[1][JD] = -cx_.d1(ihx);
+            S.del[2][JD] = bx_.d1(ihx) - ay.d1(ihy);
+        }
+        if constexpr (DIAG && sizeof(T) == 4) {
+            S.bd[0][JD] = zm_d1d(AZ, XW, dc.ih1[1]);
+            S.bd[1][JD] = -zm_d1d(AZ, 1, dc.ih1[0]);
+            S.bd[2][JD] = zm_d1d(AY, 1, dc.ih1[0]) - zm_d1d(AX, XW, dc.ih1[1]);
+        }
+#pragma unroll
+        for (int m = 0; m < 3; m++) S.q[m][J] = now[m];
+    }
+}
+
+template <typename T, int SUB, bool DIAG, bool STORE, int WPE, bool UPW = false>
+__global__ void __launch_bounds__(ZmCfg<T>::NT, WPE)
+k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
+{
+    using C = ZmCfg<T>;
+    using Z = Zm<T, SUB, DIAG, STORE, UPW>;
+    constexpr int NT = C::NT, NC = C::NC, EPL = C::EPL, XW = C::XW, PLE = C::PLE;
+    static_assert(!(DIAG && SUB != 0), "diagnostics are taken in substep 0 only");
+    __shared__ __align__(16) T lds[C::LDS];
+
+    const TileEnt te = tiles[blockIdx.x];
+    const RunDesc<T> &r = runs[te.run];
+    const int nx = r.nx, ny = r.ny, nz = r.nz;
+    const int x0 = te.xy & 0xffff, y0 = te.xy >> 16, zs = te.z0, x0s = x0 + r.xs;
+    const int len = min(r.seg, nz - zs);
+    const int K = len + 6;  // steps: planes zs-3 .. zs+len+2
+    const int par = (r.parity0 + step) & 1;
+    const int in_set = (SUB == 1) ? (par ^ 1) : par;
+    const int out_set = (SUB == 1) ? par : (par ^ 1);
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const bool flow = wave < NC / 64;
+    const int col = tid & (NC - 1);
+    const int cx = col % C::TX, cy = col / C::TX;
+    const uint64_t plane_b = (uint64_t)nx * (uint64_t)ny * sizeof(T);
+
+    // Plane copies: wave-copy t = j * NW + wave (wave-uniform) brings 64 vectors of the
+    // flow planes (t < NIF) or of the field planes (t >= NIF); every lane's source is one
+    // field's row segment, the plane is added per step.
+    const G<char> *pp[C::NLP];
+    int pdst[C::NLP];  // destination offset within a slot's regions (values; wave-uniform)
+#pragma unroll
+    for (int j = 0; j < C::NLP; j++) {
+        const int t = j * C::NW + wave;
+        int f, v;
+        if (t < C::NIF) {
+            v = min(t * 64 + lane, 4 * C::PV - 1);
+            f = v / C::PV;
+            pdst[j] = C::FLOW + t * 64 * EPL;
+        } else {
+            const int ta = min(t - C::NIF, C::NIA - 1);  // spare copies repeat the last one
+            v = min(ta * 64 + lane, 3 * C::PV - 1);
+            f = 4 + v / C::PV;
+                        pdst[j] = C::FIELD + ta * 64 * EPL;
+        }
+        const int e = (v - (f < 4 ? f : f - 4) * C::PV) * EPL;
+        const int bx = e % XW, by = e / XW;
+        const int gx = wrapi(x0s - 4 + bx, nx), gy = wrapi(y0 - 3 + by, ny);
+        pp[j] = (const G<char> *)r.buf[in_set][f] + ((uint64_t)gx + (uint64_t)nx * gy) * sizeof(T);
+    }
+    // s-2 copies and the forcing z slot (SUB 0: every lane brings the forcing slot)
+    const G<char> *sp[Z::NLS_E > 0 ? Z::NLS_E : 1];
+    bool spf[Z::NLS_E > 0 ? Z::NLS_E : 1];
+    const G<T> *fs = (const G<T> *)r.forcing + (size_t)step * (size_t)r.fstride;
+    const G<T> *fz = fs + FHEAD + EPL * nx + EPL * ny;  // z phase table
+#pragma unroll
+    for (int j = 0; j < Z::NLS_E; j++) {
+        int q = j * NT + tid;
+        spf[j] = SUB == 0 || q == C::SV;
+        if (q >= C::SV) q = C::SV - 1;
+        const int f = q / (NC / EPL), c = (q - f * (NC / EPL)) * EPL;
+        const int x = c % C::TX, y = c / C::TX;
+        const int gx = (x0s + x) % nx;
+        sp[j] = (const G<char> *)r.buf[out_set][f] + ((uint64_t)gx + (uint64_t)nx * (y0 + y)) * sizeof(T);
+    }
+    // this thread's column and its output address in a plane
+    const uint64_t gcol = (uint64_t)((x0s + cx) % nx) + (uint64_t)nx * (uint64_t)(y0 + cy);
+    LP<T> *const lb = (LP<T> *)lds;
+    LP<T> *pb0 = lb + (flow ? C::FLOW : C::FIELD) + (cy + 3) * XW + cx + 4 - (3 * XW + 3);
+    LP<T> *sb0 = lb + C::S2 + col;
+    LP<T> *xb0 = lb + C::XU + col;
+
+    KRegsFor<T, UPW> Kr;
+    Kr.load(r.c);
+    ZmK<T> Zk;
+    Zk.load(r.c, SUB);
+    const DCoef &dc = r.dc;
+
+    auto issue = [&](int k, int d) {
+        int zp = zs - 3 + k;
+        zp += zp < 0 ? nz : 0;
+        zp -= zp >= nz ? nz : 0;
+        const int zo = k >= 6 ? zs + k - 6 : zs;
+        const uint64_t zoff = (uint64_t)zp * plane_b;
+#pragma unroll
+        for (int j = 0; j < C::NLP; j++) {
+            const int dd = pdst[j] + d * (pdst[j] >= C::FIELD ? C::AREG : C::FREG);
+            __builtin_amdgcn_global_load_lds((gconst_void_t *)(pp[j] + zoff), (lds_void_t *)(lds + dd), 16, 0, 0);
+        }
+        const G<char> *fzp = (const G<char> *)(fz + EPL * zo);
+#pragma unroll
+        for (int j = 0; j < Z::NLS_E; j++) {
+            const G<char> *src = spf[j] ? fzp : sp[j] + (uint64_t)zo * plane_b;
+            __builtin_amdgcn_global_load_lds((gconst_void_t *)src,
+                                             (lds_void_t *)(lds + C::S2 + d * C::SREG + (j * NT + wave * 64) * EPL), 16,
+                                             0, 0);
+        }
+    };
+
+    // forcing head and the tile's x/y phase slots (every wave writes the same values)
+    if constexpr (STORE) {
+        constexpr int HV = FHEAD / EPL;
+        const G<T> *Ex = fs + FHEAD, *Ey = Ex + EPL * nx;
+        const G<T> *p = fs;
+        int j = lane;
+        if (j < HV) p = fs + j * EPL;
+        else if ((j -= HV) < C::TX) p = Ex + EPL * ((x0s + j) % nx);
+        else if ((j -= C::TX) < C::TY) p = Ey + EPL * (y0 + j);
+        __builtin_amdgcn_global_load_lds((gconst_void_t *)p, (lds_void_t *)(lds + C::FH), 16, 0, 0);
+    }
+    issue(0, 0);
+    if (K > 1) issue(1, 1);
+
+    // flow and field threads run separate copies of the step loop (the same waits and
+    // barriers in the same order), so that each keeps only its own state in registers
+    ZmState<T> S;
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) S.acc[m][i] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 5; i++) S.dg[i] = 0.0;
+    S.fpr = T(1);
+    S.fpi = T(0);
+    T fa[3] = {T(0), T(0), T(0)}, fb[3] = {T(0), T(0), T(0)};
+    bool fon = false;
+    const int nit = (K + 5) / 6;
+#define ZM_STEPS(ROLE)                                                                                               \
+    for (int it = 0; it < nit; it++) {                                                                               \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 0>(it * 6 + 0, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+                                                  out_set, fa, fb, fon, issue);                                       \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 1>(it * 6 + 1, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+                                                  out_set, fa, fb, fon, issue);                                       \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 2>(it * 6 + 2, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+                                                  out_set, fa, fb, fon, issue);                                       \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 3>(it * 6 + 3, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+                                                  out_set, fa, fb, fon, issue);                                       \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 4>(it * 6 + 4, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+                                                  out_set, fa, fb, fon, issue);                                       \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 5>(it * 6 + 5, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+                                                  out_set, fa, fb, fon, issue);                                       \
+    }
+    if (flow) {
+        ZM_STEPS(0)
+    } else {
+        ZM_STEPS(1)
+    }
+#undef ZM_STEPS
+
+    if constexpr (DIAG) {
+        // per-tile partials: lane sums -> wave (DPP) -> fixed-order sum over waves
+        double acc[9];
+        if (flow) {
+            acc[0] = 0.0; acc[1] = S.dg[0]; acc[2] = S.dg[1]; acc[3] = S.dg[2];
+            acc[4] = 0.0; acc[5] = 0.0; acc[6] = 0.0; acc[7] = S.dg[3]; acc[8] = S.dg[4];
+        } else {
+            acc[0] = S.dg[0]; acc[1] = 0.0; acc[2] = 0.0; acc[3] = 0.0;
+            acc[4] = S.dg[1]; acc[5] = S.dg[2]; acc[6] = S.dg[3]; acc[7] = 0.0; acc[8] = 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 9; q++) acc[q] = (q == 7) ? wave_reduce<true>(acc[q]) : wave_reduce<false>(acc[q]);
+        double *red = reinterpret_cast<double *>(lds + C::XU);
+        lds_barrier();
+        if (lane == 63) {
+#pragma unroll
+            for (int q = 0; q < 9; q++) red[wave * 9 + q] = acc[q];
+        }
+        lds_barrier();
+        if (tid < 9) {
+            double sum = red[tid];
+            for (int w = 1; w < NT / 64; w++) sum = (tid == 7) ? fmax(sum, red[w * 9 + tid]) : sum + red[w * 9 + tid];
+            ((G<double> *)r.partials)[(size_t)te.tir * DIAGW + tid] = sum;
+        }
+    }
+}
+
+}  // namespace mhd

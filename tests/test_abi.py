@@ -95,7 +95,7 @@ def test_tile_shapes_and_pinning():
     mhd = _mhd()
     n = mhd.mhd_num_tile_shapes()
     names = [mhd.mhd_tile_shape_name(i) for i in range(n)]
-    assert len(set(names)) == n and all(re.fullmatch(r"\d+x\d+x\d+/\d(\+ring|\+march)?", s) for s in names)
+    assert len(set(names)) == n and all(re.fullmatch(r"\d+x\d+x\d+/\d(\+ring|\+march)?|\d+x\d+\+zm", s) for s in names)
     p = mhd.make_params(96, 80, 72, nu=1e-3, eta=1e-3)
     default = mhd.mhd_tile_config(p)
     mhd.mhd_set_tile_shape(p, n - 1)
