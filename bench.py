@@ -218,22 +218,76 @@ def shape_sweep(mhd, n, steps=3):
     return out
 
 
-def cpu_baseline(n=512, nz=64, seed=0):
-    """The oracle, as it stands, on a bounded sample of the 512^3 workload: one full RK3
-    step of an n x n x nz periodic box (same per-cell work), all host cores."""
+def cpu_baseline(n=512, nz=64, nz1=4, seed=0):
+    """The oracle, as it stands, on bounded samples of the 512^3 workload: one full RK3
+    step of an n x n x nz periodic box on all host cores and of an n x n x nz1 box on
+    one thread (same per-cell work as 512^3)."""
     import oracle
-    rp = mi.RunParams(n, n, nz, nu=4e-4, eta=4e-4, dt=1e-3)
-    st = mi.ic_seed_noise(rp, seed, 1e-5)
     rec = mi.forcing_schedule(seed, 1, 3.0, 0.02, 0.0)
     threads = oracle.get_threads()
+    out = {}
+    for label, depth, nthr in (("all", nz, threads), ("one_thread", nz1, 1)):
+        rp = mi.RunParams(n, n, depth, nu=4e-4, eta=4e-4, dt=1e-3)
+        st = mi.ic_seed_noise(rp, seed, 1e-5)
+        oracle.set_threads(nthr)
+        try:
+            t0 = time.perf_counter()
+            oracle.step(st, rp, rec)
+            dt = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(threads)
+        cells = float(n * n * depth)
+        out[label] = dict(value=3.0 * cells / dt, seconds=dt, threads=nthr,
+                          sample=f"one RK3 step of the FP64 oracle on a {n}x{n}x{depth} periodic box "
+                                 f"(same per-cell work as 512^3; {dt:.1f} s)")
+    a = out["all"]
+    return dict(value=a["value"], unit="cell-substeps/s", cores=threads, kind="oracle", sample=a["sample"],
+                seconds=a["seconds"], cpu=_cpu_model(),
+                one_thread=dict(value=out["one_thread"]["value"], unit="cell-substeps/s", cores=1,
+                                sample=out["one_thread"]["sample"], seconds=out["one_thread"]["seconds"]))
+
+
+def config1(mhd, steps=20):
+    """The 32^3 FP64 workload in full (nu = eta = 5e-3, non-helical forcing kf = 3, f0 = 0.02,
+    A noise 1e-5, 20 steps) on the GPU and on the oracle: the per-field error of every step
+    from a shared state (the oracle advances the GPU's previous state with the same
+    record), with the oracle's and the GPU's wall times for the whole run."""
+    import oracle
+    rp = mi.RunParams(32, 32, 32, nu=5e-3, eta=5e-3, dt=1e-3, precision=8)
+    st = mi.ic_seed_noise(rp, 0, 1e-5)
+    recs = mi.forcing_schedule(0, steps, 3.0, 0.02, 0.0)
+    p = mhd.params_from(rp)
+    # GPU wall time of the whole run in one call (set-up excluded)
+    with mhd.Run(p) as run:
+        run.set_state(st)
+        run.set_forcing(recs)
+        mhd.mhd_sync(run.h)
+        t0 = time.perf_counter()
+        run.step(steps)
+        mhd.mhd_sync(run.h)
+        gpu_s = time.perf_counter() - t0
+    # per step, from a shared state
+    got = []
+    with mhd.Run(p) as run:
+        run.set_state(st)
+        run.set_forcing(recs)
+        for _ in range(steps):
+            run.step(1)
+            got.append(run.get_state())
+    inputs = [st] + got[:-1]
+    per_step = []
+    for n in range(steps):
+        want, ts = oracle.step(inputs[n].astype(np.float64), rp, [recs[n]])
+        e, _ = oracle.tolerance_error(got[n], want, ts[0], rp.dt)
+        per_step.append([float(x) for x in e])
     t0 = time.perf_counter()
-    oracle.step(st, rp, rec)
-    dt = time.perf_counter() - t0
-    cells = float(n * n * nz)
-    return dict(value=3.0 * cells / dt, unit="cell-substeps/s", cores=threads, kind="oracle",
-                sample=f"one RK3 step of the FP64 oracle on a {n}x{n}x{nz} periodic box "
-                       f"(same per-cell work as 512^3; {dt:.1f} s)",
-                seconds=dt, cpu=_cpu_model())
+    oracle.step(st, rp, recs)
+    ora_s = time.perf_counter() - t0
+    arr = np.array(per_step)
+    return dict(workload="32^3 FP64, nu=eta=5e-3, non-helical forcing kf=3, f0=0.02, A noise 1e-5, 20 steps",
+                e_f={k: float(v) for k, v in zip(mi.FIELD_NAMES, arr.max(axis=0))},
+                e_f_per_step=[max(r) for r in per_step], bar=1e-12,
+                gpu_wall_s=gpu_s, oracle_wall_s=ora_s, oracle_threads=oracle.get_threads())
 
 
 def _cpu_model():
@@ -246,10 +300,18 @@ def _cpu_model():
     return "unknown"
 
 
+def _record_latencies_ms(diag):
+    """Per-step times of one run from the device clock of its consecutive records."""
+    t = np.array([d["t_device"] for d in diag])
+    return list(np.diff(t) * 1e3)
+
+
 def ensemble(mhd, nsteps=500, alone_steps=None):
     """48 runs (32 x 64^3 + 16 x 128^3), FP32, advanced together in graph-captured
-    launches; compared with the same runs advanced one by one by the plain solver."""
-    import torch
+    launches; compared with the same runs advanced one by one by the plain solver.
+    Step latencies of both come from the device clock in each run's diagnostic records:
+    in the batch, the time between a run's consecutive steps inside the one graph
+    launch; alone, the same for the run on its own."""
     runs = mi.ensemble_runs()
     params = [mhd.make_params(r["n"], nu=r["nu"], eta=r["eta"], dt=r["dt"], precision=r["precision"])
               for r in runs]
@@ -264,17 +326,15 @@ def ensemble(mhd, nsteps=500, alone_steps=None):
         mhd.mhd_batch_run(b, nsteps, True)
         for c in ctxs:
             mhd.mhd_sync(c)
+            mhd.mhd_clear_diag(c)
         t0 = time.perf_counter()
         mhd.mhd_batch_run(b, nsteps, True)
         mhd.mhd_sync(ctxs[0])
         wall = time.perf_counter() - t0
-        # per-ensemble-step latency: eager launches, one sync per step
         lat = []
-        for _ in range(50):
-            ta = time.perf_counter()
-            mhd.mhd_batch_run(b, 1, False)
-            mhd.mhd_sync(ctxs[0])
-            lat.append((time.perf_counter() - ta) * 1e3)
+        for c in ctxs:
+            lat.extend(_record_latencies_ms(mhd.mhd_get_diag(c)))
+        tiles = sorted({mhd.mhd_ctx_tile_config(c) for c in ctxs})
         bad = sum(mhd.mhd_get_diag(c)[-1]["nonfinite"] > 0 for c in ctxs)
     finally:
         mhd.mhd_batch_destroy(b)
@@ -290,28 +350,32 @@ def ensemble(mhd, nsteps=500, alone_steps=None):
             mhd.mhd_set_forcing_random(h, r["kf"], r["f0"], r["sigma"], r["seed"])
             mhd.mhd_step(h, 2)
             mhd.mhd_sync(h)
+            mhd.mhd_clear_diag(h)
             ta = time.perf_counter()
             mhd.mhd_step(h, alone_steps)
             mhd.mhd_sync(h)
             el = time.perf_counter() - ta
             t_alone += el * nsteps / alone_steps
-            alone_lat.append(el * 1e3 / alone_steps)
+            alone_lat.extend(_record_latencies_ms(mhd.mhd_get_diag(h)))
         finally:
             mhd.mhd_destroy(h)
-    del torch
-    return dict(runs=len(runs), steps=nsteps, wall_s=wall,
+    return dict(runs=len(runs), steps=nsteps, wall_s=wall, tiles=tiles,
                 ensemble_steps_per_s=len(runs) * nsteps / wall,
                 cell_substeps_per_s=3.0 * cells * nsteps / wall,
                 effective_gbs=VALUES_PER_CELL_STEP * 4 * cells * nsteps / wall / 1e9,
                 step_latency_p50_ms=pct(lat, 50), step_latency_p99_ms=pct(lat, 99),
+                step_latency_source="device clock between each run's consecutive records, graph-replayed run",
                 alone_wall_s=t_alone, alone_ensemble_steps_per_s=len(runs) * nsteps / t_alone,
+                alone_step_latency_p50_ms=pct(alone_lat, 50), alone_step_latency_p99_ms=pct(alone_lat, 99),
                 speedup_vs_alone=t_alone / wall, nonfinite_runs=int(bad))
 
 
-def serving(mhd, nruns=40, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tick=10):
-    """First `nruns` arrivals of the Poisson trace (rate 4/s, N in {32,64,128,256}, FP32,
-    `nsteps` steps each), served with continuous batching; the FCFS one-at-a-time
-    baseline uses measured standalone service times on the same arrivals."""
+def serving(mhd, nruns=240, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tick=10):
+    """The Poisson trace (rate 4/s, N in {32,64,128,256}, FP32, `nsteps` steps each; the
+    first `nruns` arrivals, 240 = the whole trace) served with continuous batching, then
+    the same arrivals served first come, first served one at a time with the plain
+    solver (set-up, seed field, steps, tear-down per run).  Per-step latencies of both
+    come from the device clock in the runs' diagnostic records."""
     trace = mi.serving_trace(240, nsteps=nsteps)[:nruns]
     srv = mhd.mhd_server_create(int(budget_gb * 2 ** 30), slots, steps_per_tick)
     ids = []
@@ -325,57 +389,46 @@ def serving(mhd, nruns=40, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tick
             ids.append(mhd.mhd_server_submit(srv, p, r["seed"], r["a_noise"], r["kf"], r["f0"],
                                              r["sigma"], r["nsteps"]))
         for rid in ids:
-            mhd.mhd_server_wait(srv, rid, 600.0)
+            mhd.mhd_server_wait(srv, rid, 900.0)
         makespan = time.perf_counter() - t0
         st = mhd.mhd_server_stats_get(srv)
     finally:
         mhd.mhd_server_destroy(srv)
-    # baseline: each distinct run size alone with the plain solver (set-up, seed field,
-    # steps, tear-down, as a one-by-one user would run it), then FCFS over the same
-    # arrivals
-    service = {}
-    step_ms = {}
-    setup_s = {}
-    for n in sorted({r["n"] for r in trace}):
-        p = mhd.make_params(n, nu=1e-3, eta=1e-3, dt=1e-3, precision=4)
-        t_set = time.perf_counter()
+    log(f"[bench] served {nruns} runs in {makespan:.1f} s; first come, first served one at a time")
+    # baseline: the same arrivals, one run at a time, first come first served
+    fin, lat, lat_by_n = [], [], {}
+    t0 = time.perf_counter()
+    for r in trace:
+        while time.perf_counter() - t0 < r["arrival"]:
+            time.sleep(0.001)
+        p = mhd.make_params(r["n"], nu=r["nu"], eta=r["eta"], dt=r["dt"], precision=r["precision"])
         h = mhd.mhd_create(p)
         try:
-            mhd.mhd_init_seed(h, 0, 1e-5)
-            mhd.mhd_set_forcing_random(h, 3.0, 0.02, 0.0, 0)
+            mhd.mhd_init_seed(h, r["seed"], r["a_noise"])
+            mhd.mhd_set_forcing_random(h, r["kf"], r["f0"], r["sigma"], r["seed"])
+            mhd.mhd_step(h, r["nsteps"])
             mhd.mhd_sync(h)
-            t_set = time.perf_counter() - t_set
-            mhd.mhd_step(h, 5)
-            mhd.mhd_sync(h)
-            m = min(nsteps, 200)
-            ta = time.perf_counter()
-            mhd.mhd_step(h, m)
-            mhd.mhd_sync(h)
-            step_ms[n] = (time.perf_counter() - ta) * 1e3 / m
+            ls = _record_latencies_ms(mhd.mhd_get_diag(h))
         finally:
-            td = time.perf_counter()
             mhd.mhd_destroy(h)
-            t_set += time.perf_counter() - td
-        setup_s[n] = t_set
-        service[n] = step_ms[n] * nsteps / 1e3 + t_set
-    free_at, fin, lat = 0.0, [], []
-    for r in trace:
-        start = max(free_at, r["arrival"])
-        free_at = start + service[r["n"]]
-        fin.append(free_at - r["arrival"])
-        lat.extend([step_ms[r["n"]]] * 1)
-    fcfs_makespan = free_at
-    return dict(runs=nruns, steps_per_run=nsteps, makespan_s=makespan,
+        fin.append(time.perf_counter() - t0 - r["arrival"])
+        lat.extend(ls)
+        lat_by_n.setdefault(r["n"], []).extend(ls)
+    fcfs_makespan = time.perf_counter() - t0
+    return dict(runs=nruns, steps_per_run=nsteps, offered_runs_per_s=4.0, makespan_s=makespan,
                 runs_per_hour=nruns / makespan * 3600.0,
                 step_latency_p50_ms=st.lat_p50_ms, step_latency_p99_ms=st.lat_p99_ms,
+                step_latency_source="device clock between each run's consecutive records",
+                step_samples=int(st.step_samples),
                 queue_p50_s=st.queue_p50_s, queue_p99_s=st.queue_p99_s,
                 e2e_p50_s=st.e2e_p50_s, e2e_p99_s=st.e2e_p99_s,
                 completed=int(st.completed), failed=int(st.failed),
                 hbm_peak_gb=st.hbm_peak / 2 ** 30, cell_substeps_per_s=st.cell_substeps / max(st.busy_s, 1e-9),
-                fcfs_alone=dict(makespan_s=fcfs_makespan, runs_per_hour=nruns / fcfs_makespan * 3600.0,
+                fcfs_alone=dict(kind="measured: the same arrivals run one at a time, first come first served",
+                                makespan_s=fcfs_makespan, runs_per_hour=nruns / fcfs_makespan * 3600.0,
                                 e2e_p50_s=pct(fin, 50), e2e_p99_s=pct(fin, 99),
-                                step_latency_ms={str(k): v for k, v in step_ms.items()},
-                                setup_teardown_s={str(k): v for k, v in setup_s.items()}))
+                                step_latency_p50_ms=pct(lat, 50), step_latency_p99_ms=pct(lat, 99),
+                                step_latency_p50_ms_by_n={str(k): pct(v, 50) for k, v in sorted(lat_by_n.items())}))
 
 
 def main():
@@ -391,7 +444,7 @@ def main():
     ap.add_argument("--no-spectrum", action="store_true")
     ap.add_argument("--no-growth", action="store_true")
     ap.add_argument("--no-upwind", action="store_true")
-    ap.add_argument("--serve-runs", type=int, default=40)
+    ap.add_argument("--serve-runs", type=int, default=240)
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--cpu-nz", type=int, default=64)
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
@@ -469,10 +522,16 @@ def main():
         srv = serving(mhd, args.serve_runs)
         log(f"[bench] serving {srv['runs_per_hour']:.0f} runs/h, p99 step {srv['step_latency_p99_ms']:.2f} ms")
     cpu = None
+    cfg1 = None
     if not args.no_cpu:
         log("[bench] CPU oracle sample")
         cpu = cpu_baseline(args.n, args.cpu_nz)
-        log(f"[bench] oracle {cpu['value']:.3e} cell-substeps/s on {cpu['cores']} threads")
+        log(f"[bench] oracle {cpu['value']:.3e} cell-substeps/s on {cpu['cores']} threads, "
+            f"{cpu['one_thread']['value']:.3e} on one")
+        log("[bench] 32^3 FP64 workload, 20 steps, against the oracle")
+        cfg1 = config1(mhd)
+        log("[bench] 32^3: max e_f " + " ".join(f"{k}:{v:.1e}" for k, v in cfg1["e_f"].items())
+            + f"; GPU {cfg1['gpu_wall_s'] * 1e3:.1f} ms, oracle {cfg1['oracle_wall_s'] * 1e3:.0f} ms")
 
     cells = float(args.n) ** 3
     achieved = r64["sub2_gbs"]
@@ -510,6 +569,7 @@ def main():
                      "launch_ms": r64["sub2_ms"],
                      "all_substeps_gbs": r64["substep_kernel_gbs"]},
         "cpu_baseline": cpu,
+        "config1": cfg1,
         "fp32": None if r32 is None else {
             "value": r32["cell_substeps_per_s"], "ms_per_step": r32["ms_per_step"],
             "p90_ms_per_step": r32["p90_ms"], "hbm_gbs": r32["hbm_gbs"],

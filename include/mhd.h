@@ -92,6 +92,9 @@ typedef struct {
     double em, ek, urms, brms, umax, lnrho_mean;
     double b_mean[3];
     int64_t nonfinite;       /* cells holding a NaN or Inf in any field */
+    double t_device;         /* device wall clock when this record was reduced on the device
+                              * (seconds, arbitrary origin, constant rate): the difference of
+                              * two records of a run is its measured time per step */
 } mhd_diag;
 
 typedef struct mhd_ctx mhd_ctx;
@@ -275,7 +278,9 @@ typedef struct {
     int64_t submitted, admitted, completed, failed;
     int64_t ticks;
     int64_t step_samples;          /* per-run step latencies recorded */
-    double lat_p50_ms, lat_p90_ms, lat_p99_ms;   /* per-step latency of active runs */
+    double lat_p50_ms, lat_p90_ms, lat_p99_ms;   /* per-step latency of active runs: for every
+                                                  * run and step, the device-clock time between
+                                                  * its consecutive diagnostic records */
     double queue_p50_s, queue_p99_s;             /* submit -> admit */
     double e2e_p50_s, e2e_p99_s;                 /* submit -> done */
     double busy_s, wall_s;

@@ -48,7 +48,8 @@ class mhd_forcing(C.Structure):
 class mhd_diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("t", C.c_double), ("em", C.c_double), ("ek", C.c_double),
                 ("urms", C.c_double), ("brms", C.c_double), ("umax", C.c_double),
-                ("lnrho_mean", C.c_double), ("b_mean", C.c_double * 3), ("nonfinite", C.c_int64)]
+                ("lnrho_mean", C.c_double), ("b_mean", C.c_double * 3), ("nonfinite", C.c_int64),
+                ("t_device", C.c_double)]
 
 
 class mhd_run_info(C.Structure):
@@ -277,7 +278,7 @@ def mhd_get_diag(ctx: int) -> List[dict]:
 def diag_dict(d: mhd_diag) -> dict:
     return dict(step=d.step, t=d.t, em=d.em, ek=d.ek, urms=d.urms, brms=d.brms, umax=d.umax,
                 lnrho_mean=d.lnrho_mean, bx_mean=d.b_mean[0], by_mean=d.b_mean[1],
-                bz_mean=d.b_mean[2], nonfinite=d.nonfinite)
+                bz_mean=d.b_mean[2], nonfinite=d.nonfinite, t_device=d.t_device)
 
 
 def mhd_clear_diag(ctx: int) -> None:

@@ -714,6 +714,12 @@ mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *
     c->seg = SHAPES[c->shape].zm ? zm_segment(*p) : march_segment(*p, c->shape);
     c->ntiles = run_ntiles(*p, c->shape);
     c->nb2 = run_nb2(*p, c->shape);
+    {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            c->clock_hz = 1e3 * (double)khz;
+    }
     mhd_status st = ctx_alloc_aux(c);
     if (st != MHD_OK) return st;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(MHD_E_DEVICE, "stream sync failed");
@@ -822,6 +828,7 @@ mhd_status ctx_drain(mhd_ctx *c)
         d.b_mean[1] = r[9];
         d.b_mean[2] = r[10];
         d.nonfinite = (int64_t)r[11];  /* an exact count, carried as a double on the device */
+        d.t_device = r[12] / c->clock_hz;
         c->host_diag.push_back(d);
     }
     c->rcount = 0;

@@ -26,7 +26,8 @@ using G = __attribute__((address_space(1))) T;
 
 constexpr int NF = 7;
 constexpr int DIAGW = 10;  // per-tile partials: |B|^2, |u|^2, rho|u|^2, lnrho, Bx, By, Bz, max|u|^2, nonfinite, spare
-constexpr int DREC = 12;   // record: step, t, em, ek, urms, brms, umax, <lnrho>, <Bx>, <By>, <Bz>, nonfinite
+constexpr int DREC = 13;   // record: step, t, em, ek, urms, brms, umax, <lnrho>, <Bx>, <By>, <Bz>, nonfinite,
+                           // device wall clock (ticks) when the record was written
 constexpr int FHEAD = 8;   // forcing block head: a[3], b[3], on, spare
 
 // Forcing phase tables hold (cos, sin) of one index in a 16-byte slot (FP32 pads
@@ -1518,6 +1519,7 @@ __global__ void __launch_bounds__(64) k_finalize2(const RunDesc<T> *__restrict__
         o[9] = res[5] / n;
         o[10] = res[6] / n;
         o[11] = res[8];
+        o[12] = (double)wall_clock64();  // constant-rate device clock: per-step latencies of a run
     }
 }
 

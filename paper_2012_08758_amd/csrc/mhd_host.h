@@ -79,6 +79,7 @@ struct mhd_ctx {
     size_t h_stage_bytes = 0;
     hipEvent_t stage_evt = nullptr;
     int64_t rcount = 0;      // records written on the device since the last drain
+    double clock_hz = 1e8;   // rate of the device wall clock in the records
     std::vector<mhd_diag> host_diag;
     // magnetic spectrum workspace (allocated by the first mhd_spectrum call)
     void *spec_ws = nullptr;

@@ -294,6 +294,7 @@ struct Request {
     mhd_ctx *ctx = nullptr;
     std::vector<std::vector<char>> kept;   // retained final state (host)
     double em = 0, brms = 0;
+    double last_tdev = -1.0;               // device clock of the run's latest record (s)
 };
 
 static double pct(std::vector<double> v, double q)
@@ -327,7 +328,7 @@ struct mhd_server {
     int64_t next_id = 1;
     size_t in_use = 0, peak = 0;
     int64_t n_sub = 0, n_adm = 0, n_done = 0, n_fail = 0, ticks = 0;
-    std::vector<double> step_lat_ms;   // one sample per (run, step)
+    std::vector<double> step_lat_ms;   // one sample per (run, step): device clock between its records
     std::vector<double> queue_s, e2e_s;
     double busy_s = 0, cell_substeps = 0;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -456,24 +457,34 @@ void mhd_server::loop()
             set_changed = true;
         }
         if (act.empty()) continue;
-        // a run whose state went non-finite is evicted at the tick where it shows
+        // A run whose state went non-finite is evicted at the tick where it shows.  Every
+        // record carries the device clock of the moment its step was reduced on the
+        // device; the difference between a run's consecutive records is the time that
+        // run took per step, measured, wherever the other runs' launches fell.
         std::vector<Request *> finished;
+        std::vector<double> lat_new;
         for (Request *r : act) {
             mhd_ctx *c = r->ctx;
-            if (ctx_drain(c) == MHD_OK && !c->host_diag.empty() && c->host_diag.back().nonfinite > 0) r->nsteps = 0;
+            const size_t n0 = c->host_diag.size();
+            if (ctx_drain(c) == MHD_OK) {
+                for (size_t i = n0; i < c->host_diag.size(); i++) {
+                    const double td = c->host_diag[i].t_device;
+                    if (r->last_tdev >= 0.0) lat_new.push_back((td - r->last_tdev) * 1e3);
+                    r->last_tdev = td;
+                }
+                if (!c->host_diag.empty() && c->host_diag.back().nonfinite > 0) r->nsteps = 0;
+            }
             if (c->host_diag.size() > 4) c->host_diag.erase(c->host_diag.begin(), c->host_diag.end() - 4);
         }
         {
             std::lock_guard<std::mutex> lk(mu);
             ticks++;
             busy_s += tick_ms * 1e-3;
+            step_lat_ms.insert(step_lat_ms.end(), lat_new.begin(), lat_new.end());
             for (Request *r : act) {
                 const int64_t k = kof[r->ctx];
                 cell_substeps += 3.0 * (double)k * (double)r->ctx->ncell;
-                // a run's steps are spread evenly over the tick it advanced in
-                const double per = tick_ms / (double)k;
                 r->steps_done += k;
-                for (int64_t q = 0; q < k; q++) step_lat_ms.push_back(per);
                 if (r->steps_done >= r->nsteps) finished.push_back(r);
             }
         }

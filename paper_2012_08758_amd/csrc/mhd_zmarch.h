@@ -51,12 +51,10 @@ struct ZmCfg {
     static constexpr int FLOW = 0;                         // D flow regions
     static constexpr int FIELD = FLOW + D * FREG;          // D field regions
     static constexpr int S2 = FIELD + D * AREG;            // D s-2 regions (+ forcing z slot)
-    static constexpr int XU = S2 + D * SREG;               // exchange: u at the output plane [3][NC]
-    static constexpr int XJ = XU + 3 * NC;                 // exchange: J x B [3][NC]
+    static constexpr int XJ = S2 + D * SREG;               // exchange: rho^-1 J x B + f [3][NC]
     static constexpr int FH = XJ + 3 * NC;                 // forcing head and the tile's x, y phase slots
     static constexpr int NFH = FHEAD / EPL + TX + TY;
-    static constexpr int XF = FH + 64 * EPL;               // exchange: non-finite flag of A [NC]
-    static constexpr int LDS = XF + NC;
+    static constexpr int LDS = FH + 64 * EPL;
     static_assert(PLE % EPL == 0 && XW % EPL == 0, "plane rows hold whole vectors");
     static_assert(NFH <= 64, "forcing slots: one copy");
     static_assert(NC % 64 == 0, "flow and field threads fill whole waves");
@@ -227,17 +225,22 @@ struct ZmK {
 //        slot = step mod 6;
 //   acc: pending right-hand sides of u (flow) / current density (field) of the six
 //        output planes still open, slot = output step mod 6;
-//   del: per plane (slot = step mod 3) the in-plane parts held until its z parts exist:
+//   del: per plane (slot = step mod 3) what the plane's output still needs when its z
+//        parts exist:
 //        flow  g_x, g_y, d_x u_z, d_y u_z, div_xy u, R_lnrho part;
-//        field d_y A_z, -d_x A_z, d_x A_y - d_y A_x, eta (D2x + D2y) A_m.
+//        field d_y A_z, -d_x A_z, d_x A_y - d_y A_x, eta (D2x + D2y) A_m, and the flow
+//              values ln rho, u_x, u_y, u_z at the column (for rho^-1 J x B, u x B and the
+//              diagnostics, which the field thread of a column takes on).
 template <typename T>
 struct ZmState {
     T q[4][6];
     T acc[3][6];
-    T del[6][3];
-    T fpr, fpi;       // flow: forcing exp(i (k_x x + k_y y)) at the column
-    double dg[5];     // diagnostics: flow |u|^2, rho |u|^2, ln rho, max |u|^2, non-finite cells;
-                      //              field |B|^2, B_x, B_y, B_z
+    T del[10][3];
+    T fpr, fpi;       // field: forcing exp(i (k_x x + k_y y)) at the column
+    double dg[9];     // diagnostics in the order of the per-tile partials: |B|^2, |u|^2, rho |u|^2,
+                      // ln rho, B_x, B_y, B_z, max |u|^2, non-finite cells; a flow thread sums the
+                      // u and ln rho terms, a field thread the B terms and the non-finite count
+                      // (it holds all seven values of its cell)
     double bd[3][3];  // diagnostics of FP32 runs, field: the B parts of del in FP64
 };
 
@@ -256,7 +259,7 @@ __device__ __forceinline__ double zm_d1d(const PT *s, int st, double ih)
 // ROLE 0 is a flow thread, 1 a field thread.
 template <typename T, int SUB, bool DIAG, bool STORE, bool UPW, int ROLE, int J, class KR, class ISSUE>
 __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, const KR &Kr, const ZmK<T> &Zk,
-                                        const DCoef &dc, const RunDesc<T> &r, LP<T> *pb0, LP<T> *sb0, LP<T> *xb0, int col,
+                                        const DCoef &dc, const RunDesc<T> &r, LP<T> *pb0, LP<T> *sb0, LP<T> *xb0, LP<T> *cf0, int col,
                                         uint64_t gcol, uint64_t plane_b, int zs, int out_set, T (&fa)[3], T (&fb)[3],
                                         bool &fon, ISSUE &issue)
 {
@@ -273,7 +276,7 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
     // this thread's planes (pb0 points 3 rows and 3 columns before its column in slot 0
     // of its role's region), s-2 values and exchange slots; the asm keeps the compiler
     // from hoisting addresses derived from them out of the step loop
-    asm volatile("" : "+v"(pb0), "+v"(sb0), "+v"(xb0));
+    asm volatile("" : "+v"(pb0), "+v"(sb0), "+v"(xb0), "+v"(cf0));
     constexpr int CO = 3 * XW + 3;
     const LP<T> *P = pb0 + JD * (ROLE == 0 ? C::FREG : C::AREG) + CO;  // P[f * PLE] = field f of the role at the column
     const LP<T> *S2 = sb0 + JD * C::SREG;                               // S2[f * NC] = s-2 value of field f
@@ -323,54 +326,39 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
         }
     }
 
-    LP<T> *XU = xb0, *XJ = xb0 + (C::XJ - C::XU), *XF = xb0 + (C::XF - C::XU);  // [.. * NC] at the column
+    // The field thread of a column forms rho^-1 J x B + f (it holds ln rho and u of the
+    // output plane, see del) and hands it to the flow thread through LDS.
+    LP<T> *XJ = xb0;  // XJ[m * NC]: component m at the column
     if (out) {
         const T ihz = Kr.ih1[2], ih2z = Kr.ih2[2];
         if constexpr (ROLE == 0) {
             const ZCol<T> L = zcol<T, J>(S.q[0], now[0]), X = zcol<T, J>(S.q[1], now[1]);
             const ZCol<T> Y = zcol<T, J>(S.q[2], now[2]), W = zcol<T, J>(S.q[3], now[3]);
-            const T l0 = L.v[3], ux = X.v[3], uy = Y.v[3], uz = W.v[3];
-            if constexpr (STORE) {
-                XU[0] = ux;
-                XU[NC] = uy;
-                XU[2 * NC] = uz;
-            }
             if constexpr (DIAG) {
-                const double dx = (double)ux, dy = (double)uy, dz = (double)uz;
+                const double lz = (double)L.v[3], dx = (double)X.v[3], dy = (double)Y.v[3], dz = (double)W.v[3];
                 const double u2 = dx * dx + dy * dy + dz * dz;
-                S.dg[0] += u2;
-                S.dg[1] += exp((double)l0) * u2;
-                S.dg[2] += (double)l0;
-                S.dg[3] = fmax(S.dg[3], u2);
-            }
-            lds_barrier();  // u and J x B exchanged
-            if constexpr (DIAG) {
-                const bool bad = !(finite_v(l0) && finite_v(ux) && finite_v(uy) && finite_v(uz)) || XF[0] != T(0);
-                S.dg[4] += bad ? 1.0 : 0.0;
+                S.dg[1] += u2;
+                S.dg[2] += exp(lz) * u2;
+                S.dg[3] += lz;
+                S.dg[7] = fmax(S.dg[7], u2);
             }
             if constexpr (STORE) {
+                const T l0 = L.v[3], ux = X.v[3], uy = Y.v[3], uz = W.v[3];
                 const T gz = L.d1(ihz), dzx = X.d1(ihz), dzy = Y.d1(ihz), dzz = W.d1(ihz);
                 const T gx = S.del[0][JD], gy = S.del[1][JD], dxz = S.del[2][JD], dyz = S.del[3][JD];
                 const T divxy = S.del[4][JD], pl = S.del[5][JD];
                 const T nu = Kr.nu, n23 = Kr.nu2_3;
-                const T rinv = exp(-l0);
-                const T jbx = XJ[0], jby = XJ[NC], jbz = XJ[2 * NC];
                 T R[4];
                 R[0] = pl - uz * gz - dzz;
                 if constexpr (UPW) R[0] += Kr.upw[2] * fabs(uz) * L.d6();
-                R[1] = S.acc[0][PO] + nu * X.d2(ih2z) - uz * dzx + nu * (dzx * gz + dxz * gz) - n23 * dzz * gx +
-                       rinv * jbx;
-                R[2] = S.acc[1][PO] + nu * Y.d2(ih2z) - uz * dzy + nu * (dzy * gz + dyz * gz) - n23 * dzz * gy +
-                       rinv * jby;
+                R[1] = S.acc[0][PO] + nu * X.d2(ih2z) - uz * dzx + nu * (dzx * gz + dxz * gz) - n23 * dzz * gx;
+                R[2] = S.acc[1][PO] + nu * Y.d2(ih2z) - uz * dzy + nu * (dzy * gz + dyz * gz) - n23 * dzz * gy;
                 R[3] = S.acc[2][PO] + (nu + Kr.nu3) * W.d2(ih2z) - uz * dzz +
-                       nu * (T(2) * dzz * gz + dzx * gx + dzy * gy) - n23 * (divxy + dzz) * gz - Kr.cs2 * gz +
-                       rinv * jbz;
-                if (fon) {
-                    const T *Ez = lds + C::S2 + JD * C::SREG + Z::FZ;
-                    const T cr = S.fpr * Ez[0] - S.fpi * Ez[1], ci = S.fpr * Ez[1] + S.fpi * Ez[0];
-#pragma unroll
-                    for (int a = 0; a < 3; a++) R[1 + a] += fa[a] * cr + fb[a] * ci;
-                }
+                       nu * (T(2) * dzz * gz + dzx * gx + dzy * gy) - n23 * (divxy + dzz) * gz - Kr.cs2 * gz;
+                lds_barrier();  // rho^-1 J x B + f of the column is in XJ
+                R[1] += XJ[0];
+                R[2] += XJ[NC];
+                R[3] += XJ[2 * NC];
                 const T bdt = Zk.bdt, brho = Zk.brho;
                 const T v[4] = {l0, ux, uy, uz};
                 const uint64_t g = gcol + (uint64_t)zo * (plane_b / sizeof(T));
@@ -389,38 +377,25 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
         } else {
             const ZCol<T> AX = zcol<T, J>(S.q[0], now[0]), AY = zcol<T, J>(S.q[1], now[1]);
             const ZCol<T> AZ = zcol<T, J>(S.q[2], now[2]);
+            const T l0 = S.del[6][JD], ux = S.del[7][JD], uy = S.del[8][JD], uz = S.del[9][JD];
             const T dzax = AX.d1(ihz), dzay = AY.d1(ihz);
             const T bx = Zk.bext[0] + S.del[0][JD] - dzay, by = Zk.bext[1] + dzax + S.del[1][JD];
             const T bz = Zk.bext[2] + S.del[2][JD];
-            T jx = T(0), jy = T(0), jz = T(0);
             if constexpr (STORE) {
-                jx = S.acc[0][PO] - AX.d2(ih2z);
-                jy = S.acc[1][PO] - AY.d2(ih2z);
-                jz = S.acc[2][PO];
-                XJ[0] = jy * bz - jz * by;
-                XJ[NC] = jz * bx - jx * bz;
-                XJ[2 * NC] = jx * by - jy * bx;
-            }
-            if constexpr (DIAG) {
-                double Bx, By, Bz;
-                if constexpr (sizeof(T) == 8) {
-                    Bx = (double)bx;
-                    By = (double)by;
-                    Bz = (double)bz;
-                } else {
-                    Bx = dc.bext[0] + S.bd[0][JD] - AY.d1d(dc.ih1[2]);
-                    By = dc.bext[1] + AX.d1d(dc.ih1[2]) + S.bd[1][JD];
-                    Bz = dc.bext[2] + S.bd[2][JD];
+                const T jx = S.acc[0][PO] - AX.d2(ih2z);
+                const T jy = S.acc[1][PO] - AY.d2(ih2z);
+                const T jz = S.acc[2][PO];
+                const T rinv = exp(-l0);
+                T f[3] = {T(0), T(0), T(0)};
+                if (fon) {
+                    const T *Ez = lds + C::S2 + JD * C::SREG + Z::FZ;
+                    const T cr = S.fpr * Ez[0] - S.fpi * Ez[1], ci = S.fpr * Ez[1] + S.fpi * Ez[0];
+#pragma unroll
+                    for (int a = 0; a < 3; a++) f[a] = fa[a] * cr + fb[a] * ci;
                 }
-                S.dg[0] += Bx * Bx + By * By + Bz * Bz;
-                S.dg[1] += Bx;
-                S.dg[2] += By;
-                S.dg[3] += Bz;
-                XF[0] = (finite_v(AX.v[3]) && finite_v(AY.v[3]) && finite_v(AZ.v[3])) ? T(0) : T(1);
-            }
-            lds_barrier();  // u and J x B exchanged
-            if constexpr (STORE) {
-                const T ux = XU[0], uy = XU[NC], uz = XU[2 * NC];
+                XJ[0] = rinv * (jy * bz - jz * by) + f[0];
+                XJ[NC] = rinv * (jz * bx - jx * bz) + f[1];
+                XJ[2 * NC] = rinv * (jx * by - jy * bx) + f[2];
                 const T eta = Kr.eta;
                 T R[3];
                 R[0] = S.del[3][JD] + eta * AX.d2(ih2z) + (uy * bz - uz * by);
@@ -441,6 +416,26 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                     ((G<T> *)r.buf[out_set][4 + m])[g] = o;
                 }
             }
+            if constexpr (DIAG) {
+                double Bx, By, Bz;
+                if constexpr (sizeof(T) == 8) {
+                    Bx = (double)bx;
+                    By = (double)by;
+                    Bz = (double)bz;
+                } else {
+                    Bx = dc.bext[0] + S.bd[0][JD] - AY.d1d(dc.ih1[2]);
+                    By = dc.bext[1] + AX.d1d(dc.ih1[2]) + S.bd[1][JD];
+                    Bz = dc.bext[2] + S.bd[2][JD];
+                }
+                S.dg[0] += Bx * Bx + By * By + Bz * Bz;
+                S.dg[4] += Bx;
+                S.dg[5] += By;
+                S.dg[6] += Bz;
+                const bool ok = finite_v(l0) && finite_v(ux) && finite_v(uy) && finite_v(uz) && finite_v(AX.v[3]) &&
+                                finite_v(AY.v[3]) && finite_v(AZ.v[3]);
+                S.dg[8] += ok ? 0.0 : 1.0;
+            }
+            if constexpr (STORE) lds_barrier();  // XJ written
         }
     }
 
@@ -573,6 +568,13 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
             S.del[1][JD] = -cx_.d1(ihx);
             S.del[2][JD] = bx_.d1(ihx) - ay.d1(ihy);
         }
+        {  // ln rho and u of plane z' at the column, from the flow region
+            const LP<T> *F = cf0 + JD * C::FREG;
+            S.del[6][JD] = F[0];
+            S.del[7][JD] = F[PLE];
+            S.del[8][JD] = F[2 * PLE];
+            S.del[9][JD] = F[3 * PLE];
+        }
         if constexpr (DIAG && sizeof(T) == 4) {
             S.bd[0][JD] = zm_d1d(AZ, XW, dc.ih1[1]);
             S.bd[1][JD] = -zm_d1d(AZ, 1, dc.ih1[0]);
@@ -653,7 +655,8 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
     LP<T> *const lb = (LP<T> *)lds;
     LP<T> *pb0 = lb + (flow ? C::FLOW : C::FIELD) + (cy + 3) * XW + cx + 4 - (3 * XW + 3);
     LP<T> *sb0 = lb + C::S2 + col;
-    LP<T> *xb0 = lb + C::XU + col;
+    LP<T> *xb0 = lb + C::XJ + col;
+    LP<T> *cf0 = lb + C::FLOW + (cy + 3) * XW + cx + 4;
 
     KRegsFor<T, UPW> Kr;
     Kr.load(r.c);
@@ -705,7 +708,7 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
         for (int m = 0; m < 3; m++) S.acc[m][i] = T(0);
     }
 #pragma unroll
-    for (int i = 0; i < 5; i++) S.dg[i] = 0.0;
+    for (int i = 0; i < 9; i++) S.dg[i] = 0.0;
     S.fpr = T(1);
     S.fpi = T(0);
     T fa[3] = {T(0), T(0), T(0)}, fb[3] = {T(0), T(0), T(0)};
@@ -713,17 +716,17 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
     const int nit = (K + 5) / 6;
 #define ZM_STEPS(ROLE)                                                                                               \
     for (int it = 0; it < nit; it++) {                                                                               \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 0>(it * 6 + 0, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 0>(it * 6 + 0, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 1>(it * 6 + 1, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 1>(it * 6 + 1, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 2>(it * 6 + 2, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 2>(it * 6 + 2, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 3>(it * 6 + 3, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 3>(it * 6 + 3, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 4>(it * 6 + 4, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 4>(it * 6 + 4, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 5>(it * 6 + 5, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 5>(it * 6 + 5, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
     }
     if (flow) {
@@ -735,17 +738,12 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
 
     if constexpr (DIAG) {
         // per-tile partials: lane sums -> wave (DPP) -> fixed-order sum over waves
-        double acc[9];
-        if (flow) {
-            acc[0] = 0.0; acc[1] = S.dg[0]; acc[2] = S.dg[1]; acc[3] = S.dg[2];
-            acc[4] = 0.0; acc[5] = 0.0; acc[6] = 0.0; acc[7] = S.dg[3]; acc[8] = S.dg[4];
-        } else {
-            acc[0] = S.dg[0]; acc[1] = 0.0; acc[2] = 0.0; acc[3] = 0.0;
-            acc[4] = S.dg[1]; acc[5] = S.dg[2]; acc[6] = S.dg[3]; acc[7] = 0.0; acc[8] = 0.0;
-        }
+        double acc[9];  // each thread left zero the sums of the other role
+#pragma unroll
+        for (int q = 0; q < 9; q++) acc[q] = S.dg[q];
 #pragma unroll
         for (int q = 0; q < 9; q++) acc[q] = (q == 7) ? wave_reduce<true>(acc[q]) : wave_reduce<false>(acc[q]);
-        double *red = reinterpret_cast<double *>(lds + C::XU);
+        double *red = reinterpret_cast<double *>(lds + C::XJ);
         lds_barrier();
         if (lane == 63) {
 #pragma unroll

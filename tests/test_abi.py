@@ -41,7 +41,7 @@ def test_struct_layouts_match_header():
     mhd = _mhd()
     assert C.sizeof(mhd.mhd_params) == 4 * 4 + 11 * 8
     assert C.sizeof(mhd.mhd_forcing) == 4 * 4 + 6 * 8
-    assert C.sizeof(mhd.mhd_diag) == 8 + 11 * 8
+    assert C.sizeof(mhd.mhd_diag) == 8 + 12 * 8
 
 
 @pytest.mark.parametrize("bad", [
