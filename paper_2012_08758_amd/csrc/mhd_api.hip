@@ -122,10 +122,12 @@ int default_shape(const mhd_params &p, bool aligned, bool filled)
         // The z-marching kernel beats both once its columns and segments give at least
         // 1024 work-groups (256^3: 2.64 against 3.59 ms per step in FP64, 1.65 against
         // 1.81 in FP32; 512^3: 18.3 against 26.8 and 11.9 against 12.6); at 128^3 (128
-        // work-groups) the ring kernel is faster.
+        // work-groups) alone the ring kernel is faster, but in a batch that fills the chip
+        // the z-marching kernel wins at any size (48 FP32 runs of 64^3 and 128^3: 13500
+        // against 12090 run-steps per second).
         const double n = (double)p.nx * p.ny * p.nz;
         want = (n <= 64.0 * 64 * 64 && !filled) ? 8 : (p.precision == MHD_FP64 ? 9 : 11);
-        if (shape_eligible(p, SHAPE_ZM, aligned) && run_ntiles(p, SHAPE_ZM) >= 1024) want = SHAPE_ZM;
+        if (shape_eligible(p, SHAPE_ZM, aligned) && (filled || run_ntiles(p, SHAPE_ZM) >= 1024)) want = SHAPE_ZM;
     }
     while (!shape_eligible(p, want, aligned)) want = shape_fallback(want);
     return want;

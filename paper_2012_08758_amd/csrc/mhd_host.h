@@ -90,8 +90,8 @@ namespace mhd {
 
 mhd_status check_params(const mhd_params *p);
 mhd_status check_forcing(const mhd_forcing &f);
-// filled: other runs of a batch fill the chip, so a small grid need not take the
-// small tile that gives it enough work-groups alone
+// filled: other runs of a batch fill the chip, so a grid need not take the tile that
+// gives it enough work-groups alone (it takes the z-marching tile where it can)
 int default_shape(const mhd_params &p, bool aligned = true, bool filled = false);
 bool shape_eligible(const mhd_params &p, int shape, bool aligned);
 bool shape_fits(const mhd_params &p, int shape);

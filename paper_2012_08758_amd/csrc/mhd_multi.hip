@@ -24,9 +24,9 @@
 
 namespace mhd {
 
-// Work-groups (tiles per substep) that the runs of one precision in a batch must
-// bring, with the large-grid tile, for small grids to take that tile too: 16 per CU.
-constexpr int64_t BATCH_FILL = 16 * 256;
+// Cells that the runs of one precision in a batch must bring for each of them to take
+// the filled-chip tile: 16 ring work-groups of 1024 cells per CU.
+constexpr double BATCH_FILL_CELLS = 4096.0 * 1024;
 
 struct Group {
     int prec = 8;
@@ -540,18 +540,19 @@ mhd_status mhd_batch_create(const mhd_params *runs, int32_t n, void *hip_stream,
     }
     mhd_batch *b = new (std::nothrow) mhd_batch();
     if (!b) return fail(MHD_E_OOM, "host allocation failed");
-    // A grid of at most 64^3 alone takes a small tile so that its work-groups fill the
-    // chip; in a batch the runs of one precision fill it together.  When their
-    // work-groups with the large-grid tile come to BATCH_FILL or more, every run of
-    // that precision takes the large-grid choice (48 FP32 runs of 64^3 and 128^3: 6 %
-    // more run-steps per second than with the small tile on the 64^3 runs).
-    int64_t wg[2] = {0, 0};
+    // A grid alone takes the tile that fills the chip with its own work-groups (a small
+    // tile at 64^3 and below, the ring kernel up to 128^3); in a batch the runs of one
+    // precision fill it together.  When their cells come to BATCH_FILL_CELLS or more,
+    // every run of that precision takes the filled-chip choice (the z-marching kernel
+    // where the grid allows it: 48 FP32 runs of 64^3 and 128^3 make 12 % more
+    // run-steps per second with it than with the ring kernel).
+    double cells[2] = {0, 0};
     for (int32_t i = 0; i < n; i++)
-        wg[runs[i].precision == MHD_FP64] += run_ntiles(runs[i], default_shape(runs[i], true, true));
+        cells[runs[i].precision == MHD_FP64] += (double)runs[i].nx * runs[i].ny * runs[i].nz;
     mhd_status st = b->mr.init_stream(hip_stream);
     for (int32_t i = 0; i < n && st == MHD_OK; i++) {
         mhd_ctx *c = new mhd_ctx();
-        const bool filled = wg[runs[i].precision == MHD_FP64] >= BATCH_FILL;
+        const bool filled = cells[runs[i].precision == MHD_FP64] >= BATCH_FILL_CELLS;
         st = ctx_init(c, &runs[i], b->mr.stream, nullptr, filled ? default_shape(runs[i], true, true) : -1);
         c->in_batch = true;
         b->runs.push_back(c);

@@ -45,9 +45,10 @@ def _state(mhd, ctx, rp):
 
 def test_the_48_run_ensemble_mix(mhd):
     """The ensemble workload (32 x 64^3 + 16 x 128^3, FP32, nu = eta log-spaced, helical and
-    non-helical forcing, seeds 0..47) for two graph-replayed steps: sampled 64^3 runs (which
-    take the large-grid tile in the full batch) against the oracle at every step, sampled
-    128^3 runs (same tile as alone) bit for bit against the same runs alone."""
+    non-helical forcing, seeds 0..47) for two graph-replayed steps: sampled 64^3 runs
+    against the oracle at every step, sampled 128^3 runs bit for bit against the same runs
+    alone with the tile shape pinned to the one they take in the batch (the z-marching
+    tile, which neither size takes alone)."""
     runs = mi.ensemble_runs()
     rps = [_rp(r) for r in runs]
     check64, check128 = (0, 13, 31), (32, 41, 47)
@@ -57,6 +58,7 @@ def test_the_48_run_ensemble_mix(mhd):
         ctxs = [mhd.mhd_batch_ctx(b, i) for i in range(len(runs))]
         cfg = {mhd.mhd_ctx_tile_config(c) for c in ctxs}
         print("tiles in the 48-run batch:", cfg, flush=True)
+        assert cfg == {"32x8+zm"}
         for c, r in zip(ctxs, runs):
             mhd.mhd_init_seed(c, r["seed"], r["a_noise"])
             mhd.mhd_set_forcing_random(c, r["kf"], r["f0"], r["sigma"], r["seed"])
@@ -74,15 +76,21 @@ def test_the_48_run_ensemble_mix(mhd):
             want, ts = oracle.step(cur, rp, [recs[k]])
             _check(outs[i][k], want, ts[0], rp, f"ensemble run {i} (64^3) step {k + 1}")
             cur = outs[i][k].astype(np.float64)
+    names = [mhd.mhd_tile_shape_name(j) for j in range(mhd.mhd_num_tile_shapes())]
     for i in check128:
         r, rp = runs[i], rps[i]
-        with mhd.Run(mhd.params_from(rp)) as run:
-            mhd.mhd_init_seed(run.h, r["seed"], r["a_noise"])
-            mhd.mhd_set_forcing_random(run.h, r["kf"], r["f0"], r["sigma"], r["seed"])
-            for k in range(2):
-                run.step(1)
-                alone = run.get_state()
-                assert np.array_equal(outs[i][k], alone), f"ensemble run {i} (128^3) step {k + 1} differs from alone"
+        p = mhd.params_from(rp)
+        mhd.mhd_set_tile_shape(p, names.index("32x8+zm"))
+        try:
+            with mhd.Run(p) as run:
+                mhd.mhd_init_seed(run.h, r["seed"], r["a_noise"])
+                mhd.mhd_set_forcing_random(run.h, r["kf"], r["f0"], r["sigma"], r["seed"])
+                for k in range(2):
+                    run.step(1)
+                    alone = run.get_state()
+                    assert np.array_equal(outs[i][k], alone), f"ensemble run {i} (128^3) step {k + 1} differs from alone"
+        finally:
+            mhd.mhd_set_tile_shape(p, -1)
 
 
 def test_a_served_run_matches_the_oracle_on_its_first_step(mhd):

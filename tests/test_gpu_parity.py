@@ -272,6 +272,39 @@ def test_full_size_sampled_one_step(mhd, n, prec, sigma, nu):
     assert np.all(e <= TOL[prec]), e
 
 
+def test_full_size_band_every_cell_fp64(mhd):
+    """512^3 FP64 in the benchmark's launch configuration: one step from a seeded state,
+    compared on EVERY cell of a 16-plane z-band (4.2 M cells, all x and y, so every tile
+    column including the ones that wrap in x, and the band crosses a z-segment boundary
+    of the z-marching kernel at z = 256).  The oracle steps a periodic 34-plane slab cut
+    from the same input state (the band plus 9 planes on each side: three substeps of a
+    radius-3 stencil reach 9 planes, so the slab's artificial z wrap cannot reach the
+    band).  The forcing record is the first draw of the schedule with k_z = 0, whose
+    forcing does not depend on z, so that the slab sees the same forcing."""
+    n, z0, band, halo = 512, 248, 16, 9
+    rp = mi.RunParams(n, n, n, nu=4e-4, eta=4e-4, dt=1e-3, precision=8)
+    rec = next(r for r in mi.forcing_schedule(0, 200, 3.0, 0.02, 0.0) if r.k[2] == 0)
+    print(f"generating {n}^3 state", flush=True)
+    st = mi.noise_state(rp, 23, 0.05, 0.05, 0.05)
+    print("one GPU step", flush=True)
+    got, _ = gpu_run(mhd, rp, st, [rec])
+    got = got[0]
+    print(f"tile config {mhd.mhd_tile_config(mhd.params_from(rp))}; oracle on the slab", flush=True)
+    nzs = band + 2 * halo
+    planes = [(z0 - halo + j) % n for j in range(nzs)]
+    slab = np.ascontiguousarray(st[:, planes])
+    del st
+    h = rp.lz / n
+    sp = mi.RunParams(n, n, nzs, nu=rp.nu, eta=rp.eta, dt=rp.dt, precision=8, lz=nzs * h)
+    want, ts = oracle.step(slab, sp, [rec])
+    want = want[:, halo:halo + band]
+    g = got[:, z0:z0 + band]
+    e, _ = oracle.tolerance_error(g, want, ts[0], rp.dt)
+    print("512^3 fp64 band of 16 planes, every cell: e_f = " +
+          " ".join(f"{k}:{x:.2e}" for k, x in zip(mi.FIELD_NAMES, e)), flush=True)
+    assert np.all(e <= TOL[8]), e
+
+
 @pytest.mark.parametrize("n,prec,sigma,nu,checks", [(256, 8, 1.0, 1e-3, (100, 200)),
                                                     (512, 8, 0.0, 4e-4, (100,)), (512, 4, 0.0, 4e-4, (100,))])
 def test_full_size_sampled_later_steps(mhd, n, prec, sigma, nu, checks):
@@ -478,10 +511,10 @@ def test_batched_ensemble_equals_runs_alone(mhd, use_graph):
 
 
 def test_a_batch_that_fills_the_chip_gives_small_grids_the_large_tile(mhd):
-    """16 FP32 runs of 64^3 bring 4096 work-groups per substep with the large-grid tile:
-    the batch gives them that tile instead of the small one they take alone, and each
-    run still matches the oracle step by step at the FP32 bar.  Two such runs do not
-    fill the chip and keep the tile they take alone."""
+    """16 FP32 runs of 64^3 bring 2^22 cells, enough to fill the chip together: the batch
+    gives them the z-marching tile instead of the small ring tile they take alone, and
+    each run still matches the oracle step by step at the FP32 bar.  Two such runs do
+    not fill the chip and keep the tile they take alone."""
     rps = [mi.RunParams(64, 64, 64, nu=2e-3, eta=2e-3, dt=1e-3, precision=4) for _ in range(16)]
     alone_cfg = mhd.mhd_tile_config(mhd.params_from(rps[0]))
     b2 = mhd.mhd_batch_create([mhd.params_from(rp) for rp in rps[:2]])
@@ -497,7 +530,7 @@ def test_a_batch_that_fills_the_chip_gives_small_grids_the_large_tile(mhd):
         ctxs = [mhd.mhd_batch_ctx(b, i) for i in range(len(rps))]
         cfg = mhd.mhd_ctx_tile_config(ctxs[0])
         print(f"alone {alone_cfg}, in the batch {cfg}", flush=True)
-        assert cfg == "32x4x8/2+ring" and cfg != alone_cfg
+        assert cfg == "32x8+zm" and cfg != alone_cfg
         for c, st, r in zip(ctxs, states, scheds):
             for f in range(7):
                 mhd.mhd_set_field(c, f, np.ascontiguousarray(st[f]))
@@ -522,9 +555,10 @@ def test_a_batch_that_fills_the_chip_gives_small_grids_the_large_tile(mhd):
 
 
 def test_a_filled_batch_gives_an_8cubed_run_the_large_tile(mhd):
-    """An FP32 batch whose large run brings more than 4096 work-groups per substep hands
-    the 32-wide ring tile to an 8^3 run in the same batch; that run (and a 12 x 8 x 8 one)
-    still meets the FP32 bar against the oracle at every step."""
+    """An FP32 batch whose large run brings more than 2^22 cells fills the chip, so an 8^3
+    run in the same batch (too narrow for the z-marching tile) takes the 32-wide ring tile
+    instead of its small one; that run (and a 12 x 8 x 8 one) still meets the FP32 bar
+    against the oracle at every step."""
     rps = [mi.RunParams(256, 256, 128, nu=1e-3, eta=1e-3, precision=4),
            mi.RunParams(8, 8, 8, nu=4e-3, eta=3e-3, precision=4),
            mi.RunParams(12, 8, 8, nu=4e-3, eta=3e-3, precision=4)]
