@@ -26,23 +26,6 @@ mhd_status fail(mhd_status s, const std::string &msg)
     return s;
 }
 
-// ------------------------------------------------------------------ SplitMix64
-// Counter-based use of SplitMix64 (Steele, Lea, Flood 2014): output i of stream
-// (seed, sid) is mix(key + (i+1) * gamma) with key = mix(seed ^ mix(sid)).
-static const uint64_t SM_GAMMA = 0x9E3779B97F4A7C15ull;
-
-static inline uint64_t sm_mix(uint64_t z)
-{
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-static inline uint64_t sm_key(uint64_t seed, uint64_t sid) { return sm_mix(seed ^ sm_mix(sid)); }
-static inline double sm_unif(uint64_t key, uint64_t ctr)
-{
-    return (double)(sm_mix(key + (ctr + 1) * SM_GAMMA) >> 11) * (1.0 / 9007199254740992.0);
-}
-
 // ------------------------------------------------------------------ tile shapes
 
 const Shape SHAPES[NSHAPES] = {
@@ -977,65 +960,27 @@ mhd_status ctx_step(mhd_ctx *c, int64_t n)
     return c->p.precision == MHD_FP64 ? ctx_step_t<double>(c, n) : ctx_step_t<float>(c, n);
 }
 
-// Initial condition on the host, generated in parallel slices.
-// The seed field of A (three fields, x fastest), generated on the host: SplitMix64
-// counters of stream 100 + field, Box-Muller pairs.  Pure host work, so a caller can
-// run it while the device is busy.
-void init_noise_host(const mhd_params &p, uint64_t seed, double amp, std::vector<char> &out)
+// ln rho = 0, u = 0, A = the seed field of (seed, amp), into the current buffer set,
+// generated on the device in the context's stream (ordered before its next step).
+template <typename T>
+static mhd_status ctx_init_seed_t(mhd_ctx *c, uint64_t seed, double amp)
 {
-    const size_t n = (size_t)p.nx * p.ny * p.nz;
-    const int prec = p.precision;
-    out.resize(3 * n * prec);
-    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    for (int f = 4; f < NF; f++) {
-        char *dst = out.data() + (size_t)(f - 4) * n * prec;
-        const uint64_t key = sm_key(seed, 100 + f);
-        std::vector<std::thread> th;
-        for (unsigned t = 0; t < nth; t++) {
-            th.emplace_back([&, t]() {
-                const size_t npair = (n + 1) / 2;
-                const size_t lo = npair * t / nth, hi = npair * (t + 1) / nth;
-                for (size_t pi = lo; pi < hi; pi++) {
-                    const double u1 = sm_unif(key, 2 * pi), u2 = sm_unif(key, 2 * pi + 1);
-                    const double r = std::sqrt(-2.0 * std::log1p(-u1));
-                    const double z0 = amp * (r * std::cos(2.0 * M_PI * u2));
-                    const double z1 = amp * (r * std::sin(2.0 * M_PI * u2));
-                    const size_t i0 = 2 * pi, i1 = 2 * pi + 1;
-                    if (prec == MHD_FP64) {
-                        ((double *)dst)[i0] = z0;
-                        if (i1 < n) ((double *)dst)[i1] = z1;
-                    } else {
-                        ((float *)dst)[i0] = (float)z0;
-                        if (i1 < n) ((float *)dst)[i1] = (float)z1;
-                    }
-                }
-            });
-        }
-        for (auto &x : th) x.join();
-    }
-}
-
-// ln rho = 0, u = 0, A = the given seed field, into the current buffer set
-mhd_status ctx_upload_seed(mhd_ctx *c, const std::vector<char> &noise)
-{
-    const size_t bytes = c->ncell * c->p.precision;
-    if (noise.size() != 3 * bytes) return fail(MHD_E_INVALID, "seed field has the wrong size");
-    for (int f = 0; f < 4; f++)
-        if (hipMemsetAsync(c->bufs[c->parity][f], 0, bytes, c->stream) != hipSuccess)
-            return fail(MHD_E_DEVICE, "clearing the initial condition failed");
-    for (int f = 4; f < NF; f++)
-        if (hipMemcpyAsync(c->bufs[c->parity][f], noise.data() + (size_t)(f - 4) * bytes, bytes,
-                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
-            return fail(MHD_E_DEVICE, "uploading the initial condition failed");
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(MHD_E_DEVICE, "uploading the initial condition failed");
+    SeedArgs<T> a;
+    for (int f = 0; f < NF; f++) a.f[f] = (T *)c->bufs[c->parity][f];
+    for (int k = 0; k < 3; k++) a.key[k] = sm_key(seed, 104 + k);
+    a.amp = amp;
+    a.n = c->ncell;
+    const uint64_t npair = (a.n + 1) / 2;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((npair + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_seed<T>, dim3(grid), dim3(256), 0, c->stream, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("seed kernel launch failed: ") + hipGetErrorString(e));
     return MHD_OK;
 }
 
 mhd_status ctx_init_seed(mhd_ctx *c, uint64_t seed, double amp)
 {
-    std::vector<char> noise;
-    init_noise_host(c->p, seed, amp, noise);
-    return ctx_upload_seed(c, noise);
+    return c->p.precision == MHD_FP64 ? ctx_init_seed_t<double>(c, seed, amp) : ctx_init_seed_t<float>(c, seed, amp);
 }
 
 }  // namespace mhd

@@ -1523,4 +1523,56 @@ __global__ void __launch_bounds__(64) k_finalize2(const RunDesc<T> *__restrict__
     }
 }
 
+// ------------------------------------------------------------------ seed field
+// Counter-based use of SplitMix64 (Steele, Lea, Flood 2014): output i of stream
+// (seed, sid) is mix(key + (i+1) * gamma) with key = mix(seed ^ mix(sid)).  The host
+// uses the same functions for the forcing draws.
+constexpr uint64_t SM_GAMMA = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ inline uint64_t sm_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sm_key(uint64_t seed, uint64_t sid) { return sm_mix(seed ^ sm_mix(sid)); }
+__host__ __device__ inline double sm_unif(uint64_t key, uint64_t ctr)
+{
+    return (double)(sm_mix(key + (ctr + 1) * SM_GAMMA) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+template <typename T>
+struct SeedArgs {
+    T *f[NF];          // the seven fields of the current buffer set
+    uint64_t key[3];   // SplitMix64 keys of A_x, A_y, A_z (streams 100 + field index)
+    double amp;
+    uint64_t n;        // cells
+};
+
+// Initial state: ln rho = 0, u = 0, and each component of A Gaussian noise of standard
+// deviation amp, cell i (x fastest) taking value i of its stream.  Counters 2p and 2p+1
+// give the pair of cells 2p, 2p+1 by the Box-Muller transform, in FP64 and rounded
+// once to T.  One thread per pair, grid-stride.
+template <typename T>
+__global__ void __launch_bounds__(256) k_seed(SeedArgs<T> a)
+{
+    const uint64_t npair = (a.n + 1) / 2;
+    for (uint64_t pi = (uint64_t)blockIdx.x * 256 + threadIdx.x; pi < npair; pi += (uint64_t)gridDim.x * 256) {
+        const uint64_t i0 = 2 * pi, i1 = i0 + 1;
+        const bool two = i1 < a.n;
+        for (int f = 0; f < 4; f++) {
+            ((G<T> *)a.f[f])[i0] = T(0);
+            if (two) ((G<T> *)a.f[f])[i1] = T(0);
+        }
+        for (int c = 0; c < 3; c++) {
+            const double u1 = sm_unif(a.key[c], i0), u2 = sm_unif(a.key[c], i1);
+            const double r = sqrt(-2.0 * log1p(-u1));
+            const double z0 = a.amp * (r * cos(2.0 * M_PI * u2));
+            const double z1 = a.amp * (r * sin(2.0 * M_PI * u2));
+            ((G<T> *)a.f[4 + c])[i0] = (T)z0;
+            if (two) ((G<T> *)a.f[4 + c])[i1] = (T)z1;
+        }
+    }
+}
+
 }  // namespace mhd

@@ -105,8 +105,6 @@ void ctx_release(mhd_ctx *c);
 mhd_status ctx_step(mhd_ctx *c, int64_t n);
 mhd_status ctx_drain(mhd_ctx *c);
 mhd_status ctx_init_seed(mhd_ctx *c, uint64_t seed, double amp);
-void init_noise_host(const mhd_params &p, uint64_t seed, double amp, std::vector<char> &out);
-mhd_status ctx_upload_seed(mhd_ctx *c, const std::vector<char> &noise);
 mhd_status ctx_forcing_blocks(mhd_ctx *c, int64_t n0, int64_t m, void *dst);
 mhd_forcing random_forcing(double kf, double f0, double sigma, uint64_t seed, int64_t n);
 

@@ -350,8 +350,8 @@ void mhd_server::loop()
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     const bool have_ev = hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
     while (!stop_req.load()) {
-        // admission (FIFO) by footprint and free slots; admitted runs are prepared while
-        // the current tick runs on the device and join from the next tick on
+        // admission (FIFO) by footprint and free slots; admitted runs get their device
+        // state at the end of the current tick and join from the next tick on
         std::vector<Request *> admit;
         {
             std::unique_lock<std::mutex> lk(mu);
@@ -410,10 +410,7 @@ void mhd_server::loop()
             if (have_ev) (void)hipEventRecord(ev1, mr.stream);
         }
         const double ta = now();
-        // 2. meanwhile, on the host: the seed fields of the admitted runs
-        std::vector<std::vector<char>> noise(admit.size());
-        for (size_t i = 0; i < admit.size(); i++) init_noise_host(admit[i]->p, admit[i]->seed, admit[i]->a_noise, noise[i]);
-        // 3. the end of the tick
+        // 2. the end of the tick
         if (st == MHD_OK && !act.empty() && hipStreamSynchronize(mr.stream) != hipSuccess)
             st = fail(MHD_E_DEVICE, "device error in tick");
         const double tb = now();
@@ -423,12 +420,16 @@ void mhd_server::loop()
         }
         float tick_ms = (float)((tb - ta) * 1e3);
         if (have_ev && !act.empty()) (void)hipEventElapsedTime(&tick_ms, ev0, ev1);
-        // 4. device state of the admitted runs
+        // 3. device state of the admitted runs (the seed field is generated in the stream,
+        //    ahead of the next tick).  Each run takes the tile it takes alone: the groups
+        //    of a tick (one per size class) are launched one after another, so each must
+        //    fill the chip by itself (the filled-chip tile of a batch made the served
+        //    trace 25 % slower).
         for (size_t i = 0; i < admit.size(); i++) {
             Request *r = admit[i];
             mhd_ctx *c = new mhd_ctx();
             mhd_status st2 = ctx_init(c, &r->p, mr.stream, nullptr, -1);
-            if (st2 == MHD_OK) st2 = ctx_upload_seed(c, noise[i]);
+            if (st2 == MHD_OK) st2 = ctx_init_seed(c, r->seed, r->a_noise);
             if (st2 == MHD_OK) {
                 c->fmode = 2;
                 c->kf = r->kf;

@@ -432,14 +432,22 @@ def test_autotuner_picks_a_shape_that_runs_correctly(mhd):
 
 # ------------------------------------------------------------------ runtime properties
 
-def test_init_seed_matches_input_generator(mhd):
-    rp = mi.RunParams(20, 16, 12, nu=1e-3, eta=1e-3, precision=8)
-    want = mi.ic_seed_noise(rp, 42, 1e-5)
+@pytest.mark.parametrize("dims,prec", [((20, 16, 12), 8), ((21, 15, 11), 8), ((21, 15, 11), 4), ((64, 64, 64), 4)])
+def test_init_seed_matches_input_generator(mhd, dims, prec):
+    """The seed field generated on the device against the input generator: the same
+    SplitMix64 counters and Box-Muller pairs (an odd cell count leaves the last pair
+    half used); the device and host transcendentals may differ in the last bit, so
+    FP64 values agree to a few ulp and FP32 values (rounded once from FP64) to one."""
+    rp = mi.RunParams(*dims, nu=1e-3, eta=1e-3, precision=prec)
+    want = mi.ic_seed_noise(rp, 42, 1e-5, dtype=_dtype(prec))
     with mhd.Run(mhd.params_from(rp)) as run:
+        run.set_state(np.ones_like(want))      # the seed must overwrite all seven fields
         mhd.mhd_init_seed(run.h, 42, 1e-5)
         got = run.get_state()
     assert np.all(got[:4] == 0)
-    assert np.max(np.abs(got - want)) <= 1e-15 * np.max(np.abs(want))
+    rel = np.abs(got[4:].astype(np.float64) - want[4:]) / np.abs(want[4:]).astype(np.float64).clip(1e-300)
+    bound = 8 * 2.0 ** -52 if prec == 8 else 2.0 ** -23
+    assert np.max(rel) <= bound, np.max(rel)
 
 
 def test_bitwise_deterministic_and_resumable(mhd):
