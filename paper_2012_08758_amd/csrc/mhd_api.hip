@@ -48,11 +48,14 @@ const Shape SHAPES[NSHAPES] = {
     {8, 8, 4, 1, true, true},   // 13
     // z-marching kernel with register queues: nx % 32 == 0, ny % 8 == 0
     {32, 8, 1, 1, false, false, true},  // 14
+    // the same, FP32 with nx % 64 == 0: substeps 1 and 2 on 64 x 8 tiles of 1024 threads
+    {32, 8, 1, 1, false, false, true, true},  // 15
 };
 
 // the shape used when `shape` cannot run on a grid: march -> ring -> staged, same box
 int shape_fallback(int shape)
 {
+    if (shape == SHAPE_ZMW) return SHAPE_ZM;
     if (shape == SHAPE_ZM) return 9;
     if (shape == 12) return 6;
     if (shape == 13) return 8;
@@ -76,7 +79,9 @@ bool shape_eligible(const mhd_params &p, int shape, bool aligned)
 {
     if (shape < 0 || shape >= NSHAPES) return false;
     const Shape &s = SHAPES[shape];
-    if (s.zm) return aligned && p.nx % s.tx == 0 && p.ny % s.ty == 0 && p.nx % (16 / p.precision) == 0;
+    if (s.zm)
+        return aligned && p.nx % s.tx == 0 && p.ny % s.ty == 0 && p.nx % (16 / p.precision) == 0 &&
+               (!s.wide || (p.precision == MHD_FP32 && p.nx % ZM_WIDE_TX == 0));
     if (!s.pipe) return true;
     const int epl = 16 / p.precision;
     if (!(aligned && p.nx % epl == 0)) return false;
@@ -110,7 +115,10 @@ int default_shape(const mhd_params &p, bool aligned, bool filled)
         // against 12090 run-steps per second).
         const double n = (double)p.nx * p.ny * p.nz;
         want = (n <= 64.0 * 64 * 64 && !filled) ? 8 : (p.precision == MHD_FP64 ? 9 : 11);
-        if (shape_eligible(p, SHAPE_ZM, aligned) && (filled || run_ntiles(p, SHAPE_ZM) >= 1024)) want = SHAPE_ZM;
+        if (shape_eligible(p, SHAPE_ZM, aligned) && (filled || run_ntiles(p, SHAPE_ZM) >= 1024)) {
+            want = SHAPE_ZM;
+            if (shape_eligible(p, SHAPE_ZMW, aligned)) want = SHAPE_ZMW;
+        }
     }
     while (!shape_eligible(p, want, aligned)) want = shape_fallback(want);
     return want;
@@ -334,28 +342,43 @@ int zm_segment(const mhd_params &p)
     return (p.nz + nseg - 1) / nseg;
 }
 
+// z-marching columns of tw x 8 cells in z-segments of zm_segment(p) planes, in patches
+// of 32 columns (the work-groups resident on one XCD at a time), so that neighbouring
+// columns march side by side and share their x/y halo lines in L2
+static void zm_tiles(const mhd_params &p, int tw, int run, std::vector<TileEnt> &out)
+{
+    const int ty_ = SHAPES[SHAPE_ZM].ty;
+    const int ntx = p.nx / tw, nty = p.ny / ty_, seg = zm_segment(p), nseg = (p.nz + seg - 1) / seg;
+    int px = 1;
+    while (px * 2 <= ntx && px * px * 2 <= 32) px *= 2;
+    const int py = std::max(1, std::min(nty, 32 / px));
+    for (int sg = 0; sg < nseg; sg++)
+        for (int pY = 0; pY < nty; pY += py)
+            for (int pX = 0; pX < ntx; pX += px)
+                for (int ty = pY; ty < std::min(nty, pY + py); ty++)
+                    for (int tx = pX; tx < std::min(ntx, pX + px); tx++) {
+                        TileEnt t;
+                        t.run = run;
+                        t.xy = (tx * tw) | ((ty * ty_) << 16);
+                        t.z0 = sg * seg;
+                        t.tir = tx + ntx * (ty + nty * sg);
+                        out.push_back(t);
+                    }
+}
+
+void run_tiles_wide(const mhd_params &p, int run, std::vector<TileEnt> &out) { zm_tiles(p, ZM_WIDE_TX, run, out); }
+
+int run_ntiles_wide(const mhd_params &p)
+{
+    const int seg = zm_segment(p);
+    return (p.nx / ZM_WIDE_TX) * (p.ny / SHAPES[SHAPE_ZM].ty) * ((p.nz + seg - 1) / seg);
+}
+
 void run_tiles(const mhd_params &p, int shape, int run, std::vector<TileEnt> &out)
 {
     const Shape &s = SHAPES[shape];
     if (s.zm) {
-        // columns in patches of 32 (the work-groups resident on one XCD at a time), so that
-        // neighbouring columns march side by side and share their x/y halo lines in L2
-        const int ntx = p.nx / s.tx, nty = p.ny / s.ty, seg = zm_segment(p), nseg = (p.nz + seg - 1) / seg;
-        int px = 1;
-        while (px * 2 <= ntx && px * px * 2 <= 32) px *= 2;
-        const int py = std::max(1, std::min(nty, 32 / px));
-        for (int sg = 0; sg < nseg; sg++)
-            for (int pY = 0; pY < nty; pY += py)
-                for (int pX = 0; pX < ntx; pX += px)
-                    for (int ty = pY; ty < std::min(nty, pY + py); ty++)
-                        for (int tx = pX; tx < std::min(ntx, pX + px); tx++) {
-                            TileEnt t;
-                            t.run = run;
-                            t.xy = (tx * s.tx) | ((ty * s.ty) << 16);
-                            t.z0 = sg * seg;
-                            t.tir = tx + ntx * (ty + nty * sg);
-                            out.push_back(t);
-                        }
+        zm_tiles(p, s.tx, run, out);
         return;
     }
     if (s.march) {
@@ -558,11 +581,25 @@ static hipError_t launch_march(int kind, const RunDesc<T> *runs, const TileEnt *
 // per CU), FP32 at four (128 registers, two 80 KB work-groups per CU) except substep 1,
 // whose FP64 diagnostics need more registers than that (two waves per SIMD)
 template <typename T>
-static hipError_t launch_zm(int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles, int step,
-                            hipStream_t st)
+static hipError_t launch_zm(int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles, const TileEnt *wtiles,
+                            int nwtiles, int step, hipStream_t st)
 {
     constexpr int W = sizeof(T) == 8 ? 2 : 4;
     constexpr int WD = 2;
+    if constexpr (sizeof(T) == 4) {
+        // substeps 1 and 2 on 64-wide tiles: one 1024-thread work-group per CU (the LDS
+        // holds one), whose sixteen waves stay in step at every plane
+        if (wtiles && nwtiles > 0 && (kind == 1 || kind == 2 || kind == 5 || kind == 6)) {
+            const dim3 grid(nwtiles), block(ZmCfg<T, ZM_WIDE_TX>::NT);
+            switch (kind) {
+            case 1: hipLaunchKernelGGL((k_zm<T, 1, false, true, 4, false, ZM_WIDE_TX>), grid, block, 0, st, runs, wtiles, step); break;
+            case 2: hipLaunchKernelGGL((k_zm<T, 2, false, true, 4, false, ZM_WIDE_TX>), grid, block, 0, st, runs, wtiles, step); break;
+            case 5: hipLaunchKernelGGL((k_zm<T, 1, false, true, 4, true, ZM_WIDE_TX>), grid, block, 0, st, runs, wtiles, step); break;
+            default: hipLaunchKernelGGL((k_zm<T, 2, false, true, 4, true, ZM_WIDE_TX>), grid, block, 0, st, runs, wtiles, step); break;
+            }
+            return hipGetLastError();
+        }
+    }
     const dim3 grid(ntiles), block(ZmCfg<T>::NT);
     switch (kind) {
     case 0: hipLaunchKernelGGL((k_zm<T, 0, true, true, WD>), grid, block, 0, st, runs, tiles, step); break;
@@ -578,10 +615,10 @@ static hipError_t launch_zm(int kind, const RunDesc<T> *runs, const TileEnt *til
 
 template <typename T>
 hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles,
-                          int step, hipStream_t st)
+                          const TileEnt *wtiles, int nwtiles, int step, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    if (shape == SHAPE_ZM) return launch_zm<T>(kind, runs, tiles, ntiles, step, st);
+    if (SHAPES[shape].zm) return launch_zm<T>(kind, runs, tiles, ntiles, wtiles, nwtiles, step, st);
     switch (shape) {
     case 0: return launch_shape<T, 16, 8, 4, 1>(kind, runs, tiles, ntiles, step, st);
     case 1: return launch_shape<T, 32, 8, 4, 1>(kind, runs, tiles, ntiles, step, st);
@@ -613,8 +650,10 @@ hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int max_nb2, int s
     return hipGetLastError();
 }
 
-template hipError_t launch_substep<float>(int, bool, int, const RunDesc<float> *, const TileEnt *, int, int, hipStream_t);
-template hipError_t launch_substep<double>(int, bool, int, const RunDesc<double> *, const TileEnt *, int, int, hipStream_t);
+template hipError_t launch_substep<float>(int, bool, int, const RunDesc<float> *, const TileEnt *, int, const TileEnt *, int,
+                                          int, hipStream_t);
+template hipError_t launch_substep<double>(int, bool, int, const RunDesc<double> *, const TileEnt *, int, const TileEnt *, int,
+                                           int, hipStream_t);
 template hipError_t launch_finalize<float>(const RunDesc<float> *, int, int, int, hipStream_t);
 template hipError_t launch_finalize<double>(const RunDesc<double> *, int, int, int, hipStream_t);
 
@@ -641,8 +680,9 @@ static mhd_status ctx_alloc_aux(mhd_ctx *c)
     const size_t p2bytes = (size_t)c->nb2 * DIAGW * sizeof(double);
     const size_t dbytes = 1024;
     const size_t tbytes = (size_t)c->ntiles * sizeof(TileEnt);
+    const size_t wbytes = (size_t)c->ntiles_w * sizeof(TileEnt);
     c->aux_bytes = align_up(fbytes, 256) + align_up(rbytes, 256) + align_up(pbytes, 256) + align_up(p2bytes, 256) +
-                   align_up(dbytes, 256) + align_up(tbytes, 256);
+                   align_up(dbytes, 256) + align_up(tbytes, 256) + align_up(wbytes, 256);
     if (hipMalloc(&c->aux, c->aux_bytes) != hipSuccess) return fail(MHD_E_OOM, "device allocation (aux) failed");
     char *b = (char *)c->aux;
     c->d_forcing = b; b += align_up(fbytes, 256);
@@ -650,7 +690,8 @@ static mhd_status ctx_alloc_aux(mhd_ctx *c)
     c->d_partials = (double *)b; b += align_up(pbytes, 256);
     c->d_partials2 = (double *)b; b += align_up(p2bytes, 256);
     c->d_desc = b; b += align_up(dbytes, 256);
-    c->d_tiles = (TileEnt *)b;
+    c->d_tiles = (TileEnt *)b; b += align_up(tbytes, 256);
+    c->d_tiles_w = c->ntiles_w > 0 ? (TileEnt *)b : nullptr;
     c->h_stage_bytes = fbytes + dbytes;
     if (hipHostMalloc(&c->h_stage, c->h_stage_bytes, hipHostMallocDefault) != hipSuccess)
         return fail(MHD_E_OOM, "pinned host allocation failed");
@@ -661,6 +702,13 @@ static mhd_status ctx_alloc_aux(mhd_ctx *c)
     std::vector<TileEnt> ord = xcd_order(nat);
     if (hipMemcpy(c->d_tiles, ord.data(), tbytes, hipMemcpyHostToDevice) != hipSuccess)
         return fail(MHD_E_DEVICE, "tile table upload failed");
+    if (c->ntiles_w > 0) {
+        nat.clear();
+        run_tiles_wide(c->p, 0, nat);
+        ord = xcd_order(nat);
+        if (hipMemcpy(c->d_tiles_w, ord.data(), wbytes, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(MHD_E_DEVICE, "tile table upload failed");
+    }
     return MHD_OK;
 }
 
@@ -698,6 +746,7 @@ mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *
     c->xs = x_shift(*p, c->shape);
     c->seg = SHAPES[c->shape].zm ? zm_segment(*p) : march_segment(*p, c->shape);
     c->ntiles = run_ntiles(*p, c->shape);
+    c->ntiles_w = SHAPES[c->shape].wide ? run_ntiles_wide(*p) : 0;
     c->nb2 = run_nb2(*p, c->shape);
     {
         int dev = 0, khz = 0;
@@ -862,10 +911,10 @@ static mhd_status ctx_step_t(mhd_ctx *c, int64_t nsteps)
         if (st != MHD_OK) return st;
         const RunDesc<T> *d = (const RunDesc<T> *)c->d_desc;
         for (int64_t s = 0; s < m; s++) {
-            hipError_t e = launch_substep<T>(c->shape, c->fit, 0 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            hipError_t e = launch_substep<T>(c->shape, c->fit, 0 + upk, d, c->d_tiles, c->ntiles, c->d_tiles_w, c->ntiles_w, (int)s, c->stream);
             if (e == hipSuccess) e = launch_finalize<T>(d, 1, c->nb2, (int)s, c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1 + upk, d, c->d_tiles, c->ntiles, c->d_tiles_w, c->ntiles_w, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2 + upk, d, c->d_tiles, c->ntiles, c->d_tiles_w, c->ntiles_w, (int)s, c->stream);
             if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
         }
         c->rcount += m;
@@ -904,13 +953,13 @@ static mhd_status ctx_step_timed_t(mhd_ctx *c, int64_t nsteps, double kms[4], do
         for (int64_t s = 0; s < m; s++) {
             hipEvent_t *E = &ev[(size_t)(5 * s)];
             hipError_t e = hipEventRecord(E[0], c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 0 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 0 + upk, d, c->d_tiles, c->ntiles, c->d_tiles_w, c->ntiles_w, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[1], c->stream);
             if (e == hipSuccess) e = launch_finalize<T>(d, 1, c->nb2, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[2], c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 1 + upk, d, c->d_tiles, c->ntiles, c->d_tiles_w, c->ntiles_w, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[3], c->stream);
-            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2 + upk, d, c->d_tiles, c->ntiles, (int)s, c->stream);
+            if (e == hipSuccess) e = launch_substep<T>(c->shape, c->fit, 2 + upk, d, c->d_tiles, c->ntiles, c->d_tiles_w, c->ntiles_w, (int)s, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[4], c->stream);
             if (e != hipSuccess) return fail_ev(std::string("launch failed: ") + hipGetErrorString(e));
         }
@@ -948,7 +997,7 @@ static mhd_status ctx_reduce_t(mhd_ctx *c)
     mhd_status st = ctx_stage<T>(c, 0, true);
     if (st != MHD_OK) return st;
     const RunDesc<T> *d = (const RunDesc<T> *)c->d_desc;
-    hipError_t e = launch_substep<T>(c->shape, c->fit, 3, d, c->d_tiles, c->ntiles, 0, c->stream);
+    hipError_t e = launch_substep<T>(c->shape, c->fit, 3, d, c->d_tiles, c->ntiles, nullptr, 0, 0, c->stream);
     if (e == hipSuccess) e = launch_finalize<T>(d, 1, c->nb2, 0, c->stream);
     if (e != hipSuccess) return fail(MHD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     c->rcount += 1;
@@ -1190,7 +1239,7 @@ static void shape_name(int shape, char *buf, size_t len)
 {
     const Shape &s = SHAPES[shape];
     if (s.zm)
-        std::snprintf(buf, len, "%dx%d+zm", s.tx, s.ty);
+        std::snprintf(buf, len, "%dx%d+zm", s.wide ? ZM_WIDE_TX : s.tx, s.ty);
     else
         std::snprintf(buf, len, "%dx%dx%d/%d%s", s.tx, s.ty, s.tz, s.cz, s.march ? "+march" : (s.pipe ? "+ring" : ""));
 }

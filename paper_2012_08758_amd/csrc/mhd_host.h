@@ -17,9 +17,13 @@ struct Shape {
     bool pipe;   // true: direct-to-LDS ring kernel (k_pipe); false: register-staged kernel (k_substep)
     bool march;  // true: z-marching column kernel (k_march); tz is its slab depth
     bool zm;     // true: z-marching kernel with register queues (k_zm); a tx x ty column tile
+    bool wide;   // zm, FP32: substeps 1 and 2 take 64 x 8 tiles of 1024 threads (substep 0 and
+                 // the diagnostics keep the tx x ty tiles and their partials)
 };
-constexpr int NSHAPES = 15;
+constexpr int NSHAPES = 16;
 constexpr int SHAPE_ZM = 14;
+constexpr int SHAPE_ZMW = 15;
+constexpr int ZM_WIDE_TX = 64;
 extern const Shape SHAPES[NSHAPES];
 
 // steps whose forcing blocks and diagnostic records are staged at once
@@ -52,6 +56,7 @@ struct mhd_ctx {
     int xs = 0;              // x offset of the tile grid (ring kernel)
     int seg = 0;             // z-segment length of the marching kernel
     int ntiles = 0;
+    int ntiles_w = 0;        // 64-wide tiles of substeps 1 and 2 (wide shapes), else 0
     int fstride = 0;
     bool owns = false;
     bool in_batch = false;
@@ -75,6 +80,7 @@ struct mhd_ctx {
     int nb2 = 0;
     void *d_desc = nullptr;
     mhd::TileEnt *d_tiles = nullptr;
+    mhd::TileEnt *d_tiles_w = nullptr;
     void *h_stage = nullptr;
     size_t h_stage_bytes = 0;
     hipEvent_t stage_evt = nullptr;
@@ -98,6 +104,9 @@ bool shape_fits(const mhd_params &p, int shape);
 int forcing_stride(const mhd_params &p);
 int run_ntiles(const mhd_params &p, int shape);
 void run_tiles(const mhd_params &p, int shape, int run, std::vector<TileEnt> &out);
+// the 64-wide z-marching tiles of substeps 1 and 2 (shapes with `wide`)
+void run_tiles_wide(const mhd_params &p, int run, std::vector<TileEnt> &out);
+int run_ntiles_wide(const mhd_params &p);
 std::vector<TileEnt> xcd_order(const std::vector<TileEnt> &nat);
 size_t ctx_footprint(const mhd_params &p);
 mhd_status ctx_init(mhd_ctx *c, const mhd_params *p, void *stream, void *const *bufs, int shape);
@@ -113,7 +122,7 @@ void fill_desc(const mhd_ctx *c, RunDesc<T> &d, int parity0, int64_t step0, cons
                double *partials, int first_tile);
 template <typename T>
 hipError_t launch_substep(int shape, bool fit, int kind, const RunDesc<T> *runs, const TileEnt *tiles, int ntiles,
-                          int step, hipStream_t st);
+                          const TileEnt *wtiles, int nwtiles, int step, hipStream_t st);
 template <typename T>
 hipError_t launch_finalize(const RunDesc<T> *runs, int nruns, int max_nb2, int step, hipStream_t st);
 int run_nb2(const mhd_params &p, int shape);

@@ -35,8 +35,10 @@ struct Group {
     int upk = 0;               // 4 when the group's runs use upwinding (launch kinds 4-6)
     std::vector<mhd_ctx *> members;
     int ntiles = 0;
+    int ntiles_w = 0;          // 64-wide tiles of substeps 1 and 2 (wide shapes)
     int max_nb2 = 0;
     TileEnt *d_tiles = nullptr;
+    TileEnt *d_tiles_w = nullptr;
     void *d_descs = nullptr;
     void *h_descs = nullptr;   // pinned staging
     size_t desc_bytes = 0;
@@ -67,6 +69,7 @@ struct MultiRunner {
         clear_graphs();
         for (auto &g : groups) {
             if (g.d_tiles) (void)hipFree(g.d_tiles);
+            if (g.d_tiles_w) (void)hipFree(g.d_tiles_w);
             if (g.d_descs) (void)hipFree(g.d_descs);
             if (g.h_descs) (void)hipHostFree(g.h_descs);
         }
@@ -102,6 +105,7 @@ struct MultiRunner {
         clear_graphs();
         for (auto &g : groups) {
             if (g.d_tiles) (void)hipFree(g.d_tiles);
+            if (g.d_tiles_w) (void)hipFree(g.d_tiles_w);
             if (g.d_descs) (void)hipFree(g.d_descs);
             if (g.h_descs) (void)hipHostFree(g.h_descs);
         }
@@ -139,6 +143,16 @@ struct MultiRunner {
                 return fail(MHD_E_OOM, "batch: allocating tile lists failed");
             if (hipMemcpy(g.d_tiles, ord.data(), ord.size() * sizeof(TileEnt), hipMemcpyHostToDevice) != hipSuccess)
                 return fail(MHD_E_DEVICE, "batch: tile upload failed");
+            if (SHAPES[g.shape].wide) {
+                nat.clear();
+                for (size_t i = 0; i < g.members.size(); i++) run_tiles_wide(g.members[i]->p, (int)i, nat);
+                ord = xcd_order(nat);
+                g.ntiles_w = (int)ord.size();
+                if (hipMalloc(&g.d_tiles_w, ord.size() * sizeof(TileEnt)) != hipSuccess)
+                    return fail(MHD_E_OOM, "batch: allocating tile lists failed");
+                if (hipMemcpy(g.d_tiles_w, ord.data(), ord.size() * sizeof(TileEnt), hipMemcpyHostToDevice) != hipSuccess)
+                    return fail(MHD_E_DEVICE, "batch: tile upload failed");
+            }
         }
         return MHD_OK;
     }
@@ -148,10 +162,10 @@ struct MultiRunner {
     {
         const RunDesc<T> *d = (const RunDesc<T> *)g.d_descs;
         const int nr = (int)g.members.size();
-        hipError_t e = launch_substep<T>(g.shape, g.fit, 0 + g.upk, d, g.d_tiles, g.ntiles, s, stream);
+        hipError_t e = launch_substep<T>(g.shape, g.fit, 0 + g.upk, d, g.d_tiles, g.ntiles, g.d_tiles_w, g.ntiles_w, s, stream);
         if (e == hipSuccess) e = launch_finalize<T>(d, nr, g.max_nb2, s, stream);
-        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 1 + g.upk, d, g.d_tiles, g.ntiles, s, stream);
-        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 2 + g.upk, d, g.d_tiles, g.ntiles, s, stream);
+        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 1 + g.upk, d, g.d_tiles, g.ntiles, g.d_tiles_w, g.ntiles_w, s, stream);
+        if (e == hipSuccess) e = launch_substep<T>(g.shape, g.fit, 2 + g.upk, d, g.d_tiles, g.ntiles, g.d_tiles_w, g.ntiles_w, s, stream);
         return e;
     }
 

@@ -30,9 +30,9 @@
 
 namespace mhd {
 
-template <typename T>
+template <typename T, int TXV = 32>
 struct ZmCfg {
-    static constexpr int TX = 32, TY = 8, NC = TX * TY;   // columns of a tile
+    static constexpr int TX = TXV, TY = 8, NC = TX * TY;  // columns of a tile
     static constexpr int NT = 2 * NC;                      // flow + field threads
     static constexpr int NW = NT / 64;                     // waves
     static constexpr int EPL = 16 / (int)sizeof(T);        // values per 16-byte copy
@@ -54,9 +54,10 @@ struct ZmCfg {
     static constexpr int XJ = S2 + D * SREG;               // exchange: rho^-1 J x B + f [3][NC]
     static constexpr int FH = XJ + 3 * NC;                 // forcing head and the tile's x, y phase slots
     static constexpr int NFH = FHEAD / EPL + TX + TY;
-    static constexpr int LDS = FH + 64 * EPL;
+    static constexpr int NFHC = (NFH + 63) / 64;           // wave-copies of the forcing slots
+    static constexpr int LDS = FH + NFHC * 64 * EPL;
     static_assert(PLE % EPL == 0 && XW % EPL == 0, "plane rows hold whole vectors");
-    static_assert(NFH <= 64, "forcing slots: one copy");
+    static_assert(NFHC <= 2, "forcing slots: at most two copies");
     static_assert(NC % 64 == 0, "flow and field threads fill whole waves");
     // every LDS read of a thread is an immediate offset (< 64 KiB) from one base
     static_assert((D * FREG + 6 * XW) * (int)sizeof(T) < 65536 && (D * AREG + 6 * XW) * (int)sizeof(T) < 65536 &&
@@ -194,9 +195,9 @@ __device__ __forceinline__ void push3(T (&acc)[6], T q1, T q2, T q3)
     acc[PS<J, 3>::v] -= q3;
 }
 
-template <typename T, int SUB, bool DIAG, bool STORE, bool UPW>
+template <typename T, int SUB, bool DIAG, bool STORE, bool UPW, int TXV>
 struct Zm {
-    using C = ZmCfg<T>;
+    using C = ZmCfg<T, TXV>;
     static constexpr int NLS_E = STORE ? (SUB == 0 ? 1 : C::NLS) : 0;  // s-2 / forcing copies per step
     static constexpr int NL = C::NLP + NLS_E;                         // copies per step per thread
     static constexpr int NSF = STORE ? 4 : 0, NSA = STORE ? 3 : 0;     // stores per output (flow, field)
@@ -257,14 +258,14 @@ __device__ __forceinline__ double zm_d1d(const PT *s, int st, double ih)
 // steps ahead, finish the output plane z' - 3 (k >= 6), then fold plane z' into the
 // register queues and pending accumulators.  J = k mod 6 fixes every queue slot;
 // ROLE 0 is a flow thread, 1 a field thread.
-template <typename T, int SUB, bool DIAG, bool STORE, bool UPW, int ROLE, int J, class KR, class ISSUE>
+template <typename T, int SUB, bool DIAG, bool STORE, bool UPW, int TXV, int ROLE, int J, class KR, class ISSUE>
 __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, const KR &Kr, const ZmK<T> &Zk,
                                         const DCoef &dc, const RunDesc<T> &r, LP<T> *pb0, LP<T> *sb0, LP<T> *xb0, LP<T> *cf0, int col,
                                         uint64_t gcol, uint64_t plane_b, int zs, int out_set, T (&fa)[3], T (&fb)[3],
                                         bool &fon, ISSUE &issue)
 {
-    using C = ZmCfg<T>;
-    using Z = Zm<T, SUB, DIAG, STORE, UPW>;
+    using C = ZmCfg<T, TXV>;
+    using Z = Zm<T, SUB, DIAG, STORE, UPW, TXV>;
     constexpr int NC = C::NC, PLE = C::PLE, XW = C::XW;
     constexpr int JD = J % 3;                       // delayed-set slot of plane z'
     constexpr int PO = PS<J, -3>::v;                // pending slot of the output plane (= J)
@@ -585,12 +586,12 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
     }
 }
 
-template <typename T, int SUB, bool DIAG, bool STORE, int WPE, bool UPW = false>
-__global__ void __launch_bounds__(ZmCfg<T>::NT, WPE)
+template <typename T, int SUB, bool DIAG, bool STORE, int WPE, bool UPW = false, int TXV = 32>
+__global__ void __launch_bounds__((ZmCfg<T, TXV>::NT), WPE)
 k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
 {
-    using C = ZmCfg<T>;
-    using Z = Zm<T, SUB, DIAG, STORE, UPW>;
+    using C = ZmCfg<T, TXV>;
+    using Z = Zm<T, SUB, DIAG, STORE, UPW, TXV>;
     constexpr int NT = C::NT, NC = C::NC, EPL = C::EPL, XW = C::XW, PLE = C::PLE;
     static_assert(!(DIAG && SUB != 0), "diagnostics are taken in substep 0 only");
     __shared__ __align__(16) T lds[C::LDS];
@@ -689,12 +690,15 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
     if constexpr (STORE) {
         constexpr int HV = FHEAD / EPL;
         const G<T> *Ex = fs + FHEAD, *Ey = Ex + EPL * nx;
-        const G<T> *p = fs;
-        int j = lane;
-        if (j < HV) p = fs + j * EPL;
-        else if ((j -= HV) < C::TX) p = Ex + EPL * ((x0s + j) % nx);
-        else if ((j -= C::TX) < C::TY) p = Ey + EPL * (y0 + j);
-        __builtin_amdgcn_global_load_lds((gconst_void_t *)p, (lds_void_t *)(lds + C::FH), 16, 0, 0);
+#pragma unroll
+        for (int h = 0; h < C::NFHC; h++) {
+            const G<T> *p = fs;
+            int j = h * 64 + lane;
+            if (j < HV) p = fs + j * EPL;
+            else if ((j -= HV) < C::TX) p = Ex + EPL * ((x0s + j) % nx);
+            else if ((j -= C::TX) < C::TY) p = Ey + EPL * (y0 + j);
+            __builtin_amdgcn_global_load_lds((gconst_void_t *)p, (lds_void_t *)(lds + C::FH + h * 64 * EPL), 16, 0, 0);
+        }
     }
     issue(0, 0);
     if (K > 1) issue(1, 1);
@@ -716,17 +720,17 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
     const int nit = (K + 5) / 6;
 #define ZM_STEPS(ROLE)                                                                                               \
     for (int it = 0; it < nit; it++) {                                                                               \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 0>(it * 6 + 0, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 0>(it * 6 + 0, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 1>(it * 6 + 1, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 1>(it * 6 + 1, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 2>(it * 6 + 2, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 2>(it * 6 + 2, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 3>(it * 6 + 3, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 3>(it * 6 + 3, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 4>(it * 6 + 4, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 4>(it * 6 + 4, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, ROLE, 5>(it * 6 + 5, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 5>(it * 6 + 5, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
     }
     if (flow) {

@@ -48,7 +48,7 @@ def test_the_48_run_ensemble_mix(mhd):
     non-helical forcing, seeds 0..47) for two graph-replayed steps: sampled 64^3 runs
     against the oracle at every step, sampled 128^3 runs bit for bit against the same runs
     alone with the tile shape pinned to the one they take in the batch (the z-marching
-    tile, which neither size takes alone)."""
+    kernel with 64-wide tiles in substeps 1 and 2, which neither size takes alone)."""
     runs = mi.ensemble_runs()
     rps = [_rp(r) for r in runs]
     check64, check128 = (0, 13, 31), (32, 41, 47)
@@ -58,7 +58,7 @@ def test_the_48_run_ensemble_mix(mhd):
         ctxs = [mhd.mhd_batch_ctx(b, i) for i in range(len(runs))]
         cfg = {mhd.mhd_ctx_tile_config(c) for c in ctxs}
         print("tiles in the 48-run batch:", cfg, flush=True)
-        assert cfg == {"32x8+zm"}
+        assert cfg == {"64x8+zm"}
         for c, r in zip(ctxs, runs):
             mhd.mhd_init_seed(c, r["seed"], r["a_noise"])
             mhd.mhd_set_forcing_random(c, r["kf"], r["f0"], r["sigma"], r["seed"])
@@ -80,7 +80,7 @@ def test_the_48_run_ensemble_mix(mhd):
     for i in check128:
         r, rp = runs[i], rps[i]
         p = mhd.params_from(rp)
-        mhd.mhd_set_tile_shape(p, names.index("32x8+zm"))
+        mhd.mhd_set_tile_shape(p, names.index("64x8+zm"))
         try:
             with mhd.Run(p) as run:
                 mhd.mhd_init_seed(run.h, r["seed"], r["a_noise"])

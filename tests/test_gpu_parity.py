@@ -538,7 +538,7 @@ def test_a_batch_that_fills_the_chip_gives_small_grids_the_large_tile(mhd):
         ctxs = [mhd.mhd_batch_ctx(b, i) for i in range(len(rps))]
         cfg = mhd.mhd_ctx_tile_config(ctxs[0])
         print(f"alone {alone_cfg}, in the batch {cfg}", flush=True)
-        assert cfg == "32x8+zm" and cfg != alone_cfg
+        assert cfg == "64x8+zm" and cfg != alone_cfg
         for c, st, r in zip(ctxs, states, scheds):
             for f in range(7):
                 mhd.mhd_set_field(c, f, np.ascontiguousarray(st[f]))

@@ -20,7 +20,7 @@ import oracle
 pytestmark = pytest.mark.gpu
 
 TOL = {8: 1e-12, 4: 1e-5}
-ZM = 14
+ZM, ZMW = 14, 15     # 32x8 tiles; FP32 with substeps 1 and 2 on 64x8 tiles of 1024 threads
 
 
 @pytest.fixture(scope="module")
@@ -36,12 +36,13 @@ def _dtype(prec):
     return np.float64 if prec == 8 else np.float32
 
 
-def _run(mhd, rp, st, recs):
+def _run(mhd, rp, st, recs, shape=ZM):
     p = mhd.params_from(rp)
-    mhd.mhd_set_tile_shape(p, ZM)
+    mhd.mhd_set_tile_shape(p, shape)
+    want = "64x8+zm" if shape == ZMW and rp.precision == 4 and rp.nx % 64 == 0 else "32x8+zm"
     try:
         with mhd.Run(p) as run:
-            assert mhd.mhd_ctx_tile_config(run.h) == "32x8+zm"
+            assert mhd.mhd_ctx_tile_config(run.h) == want
             run.set_state(st)
             run.set_forcing(recs)
             outs = []
@@ -103,6 +104,55 @@ def test_zm_upwinding(mhd, prec):
     for n in range(2):
         want, ts = oracle.step(inputs[n], rp, [recs[n]])
         _check(got[n], want, ts[0], rp, f"zm upwind fp{8 * prec} step {n + 1}")
+
+
+WIDE_GRIDS = [
+    ((64, 8, 13), dict(bext=(0.02, -0.01, 0.03))),                    # one 64-wide tile: halos wrap twice
+    ((128, 16, 20), dict(lx=5.0, ly=2 * math.pi, lz=4.0)),            # anisotropic spacing
+    ((192, 24, 70), dict(lx=6 * math.pi, bext=(0.0, 0.0, 0.05))),     # three tiles across, one segment
+    ((64, 16, 131), {}),                                              # segments of 66 and 65 planes
+]
+
+
+@pytest.mark.parametrize("dims,kw", WIDE_GRIDS, ids=[f"{d[0]}x{d[1]}x{d[2]}" for d, _ in WIDE_GRIDS])
+def test_zm_wide_every_step(mhd, dims, kw):
+    """FP32 with substeps 1 and 2 on 64-wide tiles (substep 0 and its diagnostics on the
+    32-wide ones), every step against the oracle."""
+    rp = mi.RunParams(*dims, nu=3e-3, eta=2e-3, dt=1e-3, precision=4, **kw)
+    st = mi.noise_state(rp, 70 + dims[2], 0.2, 0.2, 0.2, dtype=np.float32)
+    recs = mi.forcing_schedule(8, 3, 3.0, 0.05, 1.0 if dims[0] != 128 else 0.0)
+    got, diag = _run(mhd, rp, st, recs, ZMW)
+    inputs = [st.astype(np.float64)] + [g.astype(np.float64) for g in got]
+    for n in range(3):
+        want, ts = oracle.step(inputs[n], rp, [recs[n]])
+        _check(got[n], want, ts[0], rp, f"zm wide {dims} step {n + 1}")
+    for n, rec in enumerate(diag):
+        ref = oracle.diag(inputs[n], rp)
+        for k in ("em", "ek", "urms", "brms", "umax", "lnrho_mean"):
+            assert abs(rec[k] - ref[k]) <= 1e-12 * max(abs(ref[k]), 1e-300), (n, k, rec[k], ref[k])
+
+
+def test_zm_wide_upwinding(mhd):
+    rp = mi.RunParams(64, 48, 40, nu=3e-3, eta=2e-3, dt=1e-3, precision=4, upwind=1.0)
+    st = mi.noise_state(rp, 96, 0.2, 0.3, 0.2, dtype=np.float32)
+    recs = mi.forcing_schedule(6, 2, 3.0, 0.05, 0.5)
+    got, _ = _run(mhd, rp, st, recs, ZMW)
+    inputs = [st.astype(np.float64)] + [g.astype(np.float64) for g in got]
+    for n in range(2):
+        want, ts = oracle.step(inputs[n], rp, [recs[n]])
+        _check(got[n], want, ts[0], rp, f"zm wide upwind step {n + 1}")
+
+
+def test_zm_wide_and_narrow_tiles_agree_bit_for_bit(mhd):
+    """The 64-wide and 32-wide FP32 kernels do the same arithmetic per cell in the same
+    order, so the two tilings give the same bits."""
+    rp = mi.RunParams(128, 32, 48, nu=3e-3, eta=2e-3, dt=1e-3, precision=4)
+    st = mi.noise_state(rp, 5, 0.2, 0.2, 0.2, dtype=np.float32)
+    recs = mi.forcing_schedule(9, 2, 3.0, 0.05, 1.0)
+    a, _ = _run(mhd, rp, st, recs, ZM)
+    b, _ = _run(mhd, rp, st, recs, ZMW)
+    for n in range(2):
+        assert np.array_equal(a[n], b[n]), n
 
 
 def test_zm_counts_nonfinite_cells_once(mhd):
