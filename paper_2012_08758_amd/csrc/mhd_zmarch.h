@@ -70,6 +70,22 @@ struct ZmCfg {
 template <typename T>
 using LP = __attribute__((address_space(3))) T;
 
+// LDS reads of the stencils.  FP64 values are read one by one (ds_read_b64 at a 16-bit
+// immediate offset from the step's base): left to itself the compiler merges pairs into
+// ds_read2_b64, whose 8-bit offsets need a fresh base VGPR (one v_add per pair) across
+// fields and rows, 23-29 extra VALU operations per plane; the volatile reads keep them
+// apart (512^3 substep 2: 6.27 -> 5.77 ms).  FP32 keeps the merged reads: its kernels
+// issue four waves per SIMD and are VALU-bound, and there the doubled LDS issue cost more
+// than the adds (3.17 -> 3.21 ms).
+template <class PT>
+__device__ __forceinline__ auto ldv(const PT *p)
+{
+    if constexpr (sizeof(*p) == 8)
+        return *(const volatile PT *)p;
+    else
+        return *p;
+}
+
 // Folded stencil weights for the pushes of the mixed derivatives.
 template <typename T>
 struct ZmW {
@@ -104,10 +120,10 @@ struct Pairs {
     template <class PT>
     __device__ __forceinline__ void load(const PT *s, int st)
     {
-        c = s[0];
+        c = ldv(s);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            const T a = s[(k + 1) * st], b = s[-(k + 1) * st];
+            const T a = ldv(s + (k + 1) * st), b = ldv(s - (k + 1) * st);
             p[k] = a + b;
             d[k] = a - b;
         }
@@ -125,8 +141,9 @@ template <typename T, class PT>
 __device__ __forceinline__ T zm_dxy(const PT *s, int sy, T ihm)
 {
     const int p = 1 + sy, q = 1 - sy;
-    return ihm * (T(W2_1) * ((s[p] + s[-p]) - (s[q] + s[-q])) + T(W2_2) * ((s[2 * p] + s[-2 * p]) - (s[2 * q] + s[-2 * q])) +
-                  T(W2_3) * ((s[3 * p] + s[-3 * p]) - (s[3 * q] + s[-3 * q])));
+    return ihm * (T(W2_1) * ((ldv(s + p) + ldv(s - p)) - (ldv(s + q) + ldv(s - q))) +
+                  T(W2_2) * ((ldv(s + 2 * p) + ldv(s - 2 * p)) - (ldv(s + 2 * q) + ldv(s - 2 * q))) +
+                  T(W2_3) * ((ldv(s + 3 * p) + ldv(s - 3 * p)) - (ldv(s + 3 * q) + ldv(s - 3 * q))));
 }
 
 // z derivatives at the output plane from a register queue: q[(j + i) % 6] holds the
@@ -303,27 +320,27 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
     T now[4];
     if constexpr (ROLE == 0) {
         const LP<T> *L0 = P, *X = P + PLE, *Y = P + 2 * PLE, *W = P + 3 * PLE;
-        now[0] = L0[0];
-        now[1] = X[0];
-        now[2] = Y[0];
-        now[3] = W[0];
+        now[0] = ldv(L0);
+        now[1] = ldv(X);
+        now[2] = ldv(Y);
+        now[3] = ldv(W);
         if constexpr (STORE) {
             const T k3x = Kr.nu3 * Kr.ihm[1] * T(W2_3), k3y = Kr.nu3 * Kr.ihm[2] * T(W2_3);
-            S.acc[0][PO] += k3x * (W[3] - W[-3]);
-            S.acc[1][PO] += k3y * (W[3 * XW] - W[-3 * XW]);
-            S.acc[2][PO] += k3x * (X[3] - X[-3]) + k3y * (Y[3 * XW] - Y[-3 * XW]);
+            S.acc[0][PO] += k3x * (ldv(W + 3) - ldv(W - 3));
+            S.acc[1][PO] += k3y * (ldv(W + 3 * XW) - ldv(W - 3 * XW));
+            S.acc[2][PO] += k3x * (ldv(X + 3) - ldv(X - 3)) + k3y * (ldv(Y + 3 * XW) - ldv(Y - 3 * XW));
         }
     } else {
         const LP<T> *AX = P, *AY = P + PLE, *AZ = P + 2 * PLE;
-        now[0] = AX[0];
-        now[1] = AY[0];
-        now[2] = AZ[0];
+        now[0] = ldv(AX);
+        now[1] = ldv(AY);
+        now[2] = ldv(AZ);
         now[3] = T(0);
         if constexpr (STORE) {
             const T k3x = Kr.ihm[1] * T(W2_3), k3y = Kr.ihm[2] * T(W2_3);
-            S.acc[0][PO] += k3x * (AZ[3] - AZ[-3]);
-            S.acc[1][PO] += k3y * (AZ[3 * XW] - AZ[-3 * XW]);
-            S.acc[2][PO] += k3x * (AX[3] - AX[-3]) + k3y * (AY[3 * XW] - AY[-3 * XW]);
+            S.acc[0][PO] += k3x * (ldv(AZ + 3) - ldv(AZ - 3));
+            S.acc[1][PO] += k3y * (ldv(AZ + 3 * XW) - ldv(AZ - 3 * XW));
+            S.acc[2][PO] += k3x * (ldv(AX + 3) - ldv(AX - 3)) + k3y * (ldv(AY + 3 * XW) - ldv(AY - 3 * XW));
         }
     }
 
