@@ -151,6 +151,12 @@ static void fill_coef(const mhd_params &p, Coef<T> &c, DCoef &dc)
         dc.bext[a] = p.bext[a];
     }
     for (int a = 0; a < 3; a++) c.upw[a] = (T)(p.upwind / (60.0 * h[a]));
+    const double w1[3] = {W1_1, W1_2, W1_3}, w2[4] = {W2_0, W2_1, W2_2, W2_3};
+    for (int a = 0; a < 2; a++) {
+        for (int k = 0; k < 3; k++) c.w1[a][k] = (T)(w1[k] / h[a]);
+        for (int k = 0; k < 4; k++) c.w2[a][k] = (T)(w2[k] / (h[a] * h[a]));
+    }
+    for (int k = 0; k < 3; k++) c.wm[k] = (T)(w2[k + 1] / (4.0 * h[0] * h[1]));
     for (int s = 0; s < 3; s++) {
         c.bdt[s] = (T)(RK_B[s] * p.dt);
         c.brho[s] = s == 0 ? (T)0 : (T)(RK_B[s] * RK_A[s] / RK_B[s - 1]);

@@ -52,6 +52,10 @@ struct Coef {
     T bdt[3];     // beta_s * dt
     T brho[3];    // beta_s * alpha_s / beta_{s-1} (0 for s = 0)
     T upw[3];     // upwinding of the continuity advection: c / (60 h_axis)
+    // the same stencil weights scaled by the inverse spacings, x and y (z-marching kernel)
+    T w1[2][3];   // W1_s / h_axis, s = 1..3
+    T w2[2][4];   // W2_s / h_axis^2, s = 0..3
+    T wm[3];      // W2_s / (4 h_x h_y), s = 1..3 (diagonal x-y derivative)
 };
 
 struct DCoef {      // FP64 inverse spacings and mean field, for the diagnostics

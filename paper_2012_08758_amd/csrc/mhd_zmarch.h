@@ -129,6 +129,9 @@ struct Pairs {
         }
     }
     __device__ __forceinline__ T d1(T ih) const { return ih * (T(W1_1) * d[0] + T(W1_2) * d[1] + T(W1_3) * d[2]); }
+    // with the weights already divided by the spacing (one multiply fewer)
+    __device__ __forceinline__ T d1w(const T (&w)[3]) const { return w[0] * d[0] + w[1] * d[1] + w[2] * d[2]; }
+    __device__ __forceinline__ T d2w(const T (&w)[4]) const { return w[0] * c + w[1] * p[0] + w[2] * p[1] + w[3] * p[2]; }
     __device__ __forceinline__ T d2(T ih2) const
     {
         return ih2 * (T(W2_0) * c + T(W2_1) * p[0] + T(W2_2) * p[1] + T(W2_3) * p[2]);
@@ -136,15 +139,39 @@ struct Pairs {
     __device__ __forceinline__ T d6() const { return T(-20) * c + T(15) * p[0] + T(-6) * p[1] + p[2]; }
 };
 
-// d_x d_y from the two diagonals through s[0] (rows of stride sy)
+// d_x d_y from the two diagonals through s[0] (rows of stride sy); w = the diagonal
+// weights divided by 4 h_x h_y
 template <typename T, class PT>
-__device__ __forceinline__ T zm_dxy(const PT *s, int sy, T ihm)
+__device__ __forceinline__ T zm_dxy(const PT *s, int sy, const T (&w)[3])
 {
     const int p = 1 + sy, q = 1 - sy;
-    return ihm * (T(W2_1) * ((ldv(s + p) + ldv(s - p)) - (ldv(s + q) + ldv(s - q))) +
-                  T(W2_2) * ((ldv(s + 2 * p) + ldv(s - 2 * p)) - (ldv(s + 2 * q) + ldv(s - 2 * q))) +
-                  T(W2_3) * ((ldv(s + 3 * p) + ldv(s - 3 * p)) - (ldv(s + 3 * q) + ldv(s - 3 * q))));
+    return w[0] * ((ldv(s + p) + ldv(s - p)) - (ldv(s + q) + ldv(s - q))) +
+           w[1] * ((ldv(s + 2 * p) + ldv(s - 2 * p)) - (ldv(s + 2 * q) + ldv(s - 2 * q))) +
+           w[2] * ((ldv(s + 3 * p) + ldv(s - 3 * p)) - (ldv(s + 3 * q) + ldv(s - 3 * q)));
 }
+
+// in-plane stencil weights divided by the spacings, read once and pinned in scalar
+// registers
+template <typename T>
+struct ZmWts {
+    T w1x[3], w1y[3], w2x[4], w2y[4], wm[3];
+    __device__ __forceinline__ void load(const Coef<T> &c)
+    {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            w1x[k] = c.w1[0][k];
+            w1y[k] = c.w1[1][k];
+            wm[k] = c.wm[k];
+            asm volatile("" : "+s"(w1x[k]), "+s"(w1y[k]), "+s"(wm[k]));
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            w2x[k] = c.w2[0][k];
+            w2y[k] = c.w2[1][k];
+            asm volatile("" : "+s"(w2x[k]), "+s"(w2y[k]));
+        }
+    }
+};
 
 // z derivatives at the output plane from a register queue: q[(j + i) % 6] holds the
 // plane z' - 6 + i' ... see the callers; here v[0..6] = planes zo-3 .. zo+3.
@@ -227,8 +254,10 @@ struct Zm {
 template <typename T>
 struct ZmK {
     T bdt, brho, bext[3];
+    ZmWts<T> w;
     __device__ __forceinline__ void load(const Coef<T> &c, int sub)
     {
+        w.load(c);
         bdt = c.bdt[sub];
         brho = c.brho[sub];
 #pragma unroll
@@ -277,7 +306,7 @@ __device__ __forceinline__ double zm_d1d(const PT *s, int st, double ih)
 // ROLE 0 is a flow thread, 1 a field thread.
 template <typename T, int SUB, bool DIAG, bool STORE, bool UPW, int TXV, int ROLE, int J, class KR, class ISSUE>
 __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, const KR &Kr, const ZmK<T> &Zk,
-                                        const DCoef &dc, const RunDesc<T> &r, LP<T> *pb0, LP<T> *sb0, LP<T> *xb0, LP<T> *cf0, int col,
+                                        const DCoef &dc, const RunDesc<T> &r, LP<T> *&pb0, LP<T> *&sb0, LP<T> *&xb0, LP<T> *&cf0, int col,
                                         uint64_t gcol, uint64_t plane_b, int zs, int out_set, T (&fa)[3], T (&fb)[3],
                                         bool &fon, ISSUE &issue)
 {
@@ -469,7 +498,6 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
     if constexpr (ROLE == 0) {
         const LP<T> *L0 = P, *X = P + PLE, *Y = P + 2 * PLE, *W = P + 3 * PLE;
         if constexpr (STORE) {
-            const T ihx = Kr.ih1[0], ihy = Kr.ih1[1], i2x = Kr.ih2[0], i2y = Kr.ih2[1];
             const T nu = Kr.nu, nu3 = Kr.nu3, n23 = Kr.nu2_3;
             const T kx = nu3 * Kr.ihm[1], ky = nu3 * Kr.ihm[2];
             const T ux = now[1], uy = now[2];
@@ -478,8 +506,8 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 Pairs<T> lx, ly;
                 lx.load(L0, 1);
                 ly.load(L0, XW);
-                gx = lx.d1(ihx);
-                gy = ly.d1(ihy);
+                gx = lx.d1w(Zk.w.w1x);
+                gy = ly.d1w(Zk.w.w1y);
                 pl = -(ux * gx + uy * gy);
                 if constexpr (UPW) pl += Kr.upw[0] * fabs(ux) * lx.d6() + Kr.upw[1] * fabs(uy) * ly.d6();
             }
@@ -489,12 +517,12 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 Pairs<T> a, b;
                 a.load(X, 1);
                 b.load(X, XW);
-                dxx = a.d1(ihx);
-                dyx = b.d1(ihy);
-                const T d2xx = a.d2(i2x), d2yx = b.d2(i2y);
+                dxx = a.d1w(Zk.w.w1x);
+                dyx = b.d1w(Zk.w.w1y);
+                const T d2xx = a.d2w(Zk.w.w2x), d2yx = b.d2w(Zk.w.w2y);
                 S.acc[0][PN] += nu * (d2xx + d2yx) + nu3 * d2xx - (ux * dxx + uy * dyx) + nu * (T(2) * dxx * gx + dyx * gy) -
                                 Kr.cs2 * gx;
-                S.acc[1][PN] += nu3 * zm_dxy(X, XW, Kr.ihm[0]);
+                S.acc[1][PN] += nu3 * zm_dxy(X, XW, Zk.w.wm);
                 push3<T, J>(S.acc[2], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
             }
             // u_y
@@ -503,12 +531,12 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 Pairs<T> a, b;
                 a.load(Y, 1);
                 b.load(Y, XW);
-                const T dxy = a.d1(ihx);
-                dyy = b.d1(ihy);
-                const T d2xy = a.d2(i2x), d2yy = b.d2(i2y);
+                const T dxy = a.d1w(Zk.w.w1x);
+                dyy = b.d1w(Zk.w.w1y);
+                const T d2xy = a.d2w(Zk.w.w2x), d2yy = b.d2w(Zk.w.w2y);
                 S.acc[1][PN] += nu * (d2xy + d2yy) + nu3 * d2yy - (ux * dxy + uy * dyy) + nu * (dxy * gx + T(2) * dyy * gy) +
                                 nu * dyx * gx - Kr.cs2 * gy;
-                S.acc[0][PN] += nu * dxy * gy + nu3 * zm_dxy(Y, XW, Kr.ihm[0]);
+                S.acc[0][PN] += nu * dxy * gy + nu3 * zm_dxy(Y, XW, Zk.w.wm);
                 push3<T, J>(S.acc[2], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
             }
             const T divxy = dxx + dyy;
@@ -520,8 +548,8 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 Pairs<T> a, b;
                 a.load(W, 1);
                 b.load(W, XW);
-                const T dxz = a.d1(ihx), dyz = b.d1(ihy);
-                S.acc[2][PN] += nu * (a.d2(i2x) + b.d2(i2y)) - (ux * dxz + uy * dyz) + nu * (dxz * gx + dyz * gy);
+                const T dxz = a.d1w(Zk.w.w1x), dyz = b.d1w(Zk.w.w1y);
+                S.acc[2][PN] += nu * (a.d2w(Zk.w.w2x) + b.d2w(Zk.w.w2y)) - (ux * dxz + uy * dyz) + nu * (dxz * gx + dyz * gy);
                 push3<T, J>(S.acc[0], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
                 push3<T, J>(S.acc[1], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
                 S.del[2][JD] = dxz;
@@ -536,19 +564,18 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
         for (int f = 0; f < 4; f++) S.q[f][J] = now[f];
     } else {
         const LP<T> *AX = P, *AY = P + PLE, *AZ = P + 2 * PLE;
-        const T ihx = Kr.ih1[0], ihy = Kr.ih1[1];
         if constexpr (STORE) {
-            const T i2x = Kr.ih2[0], i2y = Kr.ih2[1], eta = Kr.eta;
+            const T eta = Kr.eta;
             const T kx = Kr.ihm[1], ky = Kr.ihm[2];
             T dyax;
             {  // A_x: j_x -= D2y A_x, j_y += D_xy A_x, j_z += D_xz A_x (push), B_z -= d_y A_x
                 Pairs<T> a, b;
                 a.load(AX, 1);
                 b.load(AX, XW);
-                const T d2x = a.d2(i2x), d2y = b.d2(i2y);
-                dyax = b.d1(ihy);
+                const T d2x = a.d2w(Zk.w.w2x), d2y = b.d2w(Zk.w.w2y);
+                dyax = b.d1w(Zk.w.w1y);
                 S.acc[0][PN] -= d2y;
-                S.acc[1][PN] += zm_dxy(AX, XW, Kr.ihm[0]);
+                S.acc[1][PN] += zm_dxy(AX, XW, Zk.w.wm);
                 S.del[3][JD] = eta * (d2x + d2y);
                 push3<T, J>(S.acc[2], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
             }
@@ -556,10 +583,10 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 Pairs<T> a, b;
                 a.load(AY, 1);
                 b.load(AY, XW);
-                const T d2x = a.d2(i2x), d2y = b.d2(i2y);
-                S.del[2][JD] = a.d1(ihx) - dyax;
+                const T d2x = a.d2w(Zk.w.w2x), d2y = b.d2w(Zk.w.w2y);
+                S.del[2][JD] = a.d1w(Zk.w.w1x) - dyax;
                 S.acc[1][PN] -= d2x;
-                S.acc[0][PN] += zm_dxy(AY, XW, Kr.ihm[0]);
+                S.acc[0][PN] += zm_dxy(AY, XW, Zk.w.wm);
                 S.del[4][JD] = eta * (d2x + d2y);
                 push3<T, J>(S.acc[2], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
             }
@@ -567,10 +594,10 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 Pairs<T> a, b;
                 a.load(AZ, 1);
                 b.load(AZ, XW);
-                const T d2x = a.d2(i2x), d2y = b.d2(i2y);
+                const T d2x = a.d2w(Zk.w.w2x), d2y = b.d2w(Zk.w.w2y);
                 S.acc[2][PN] -= d2x + d2y;
-                S.del[0][JD] = b.d1(ihy);
-                S.del[1][JD] = -a.d1(ihx);
+                S.del[0][JD] = b.d1w(Zk.w.w1y);
+                S.del[1][JD] = -a.d1w(Zk.w.w1x);
                 S.del[5][JD] = eta * (d2x + d2y);
                 push3<T, J>(S.acc[0], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
                 push3<T, J>(S.acc[1], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
@@ -582,9 +609,9 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
             bx_.load(AY, 1);
             cx_.load(AZ, 1);
             cy_.load(AZ, XW);
-            S.del[0][JD] = cy_.d1(ihy);
-            S.del[1][JD] = -cx_.d1(ihx);
-            S.del[2][JD] = bx_.d1(ihx) - ay.d1(ihy);
+            S.del[0][JD] = cy_.d1w(Zk.w.w1y);
+            S.del[1][JD] = -cx_.d1w(Zk.w.w1x);
+            S.del[2][JD] = bx_.d1w(Zk.w.w1x) - ay.d1w(Zk.w.w1y);
         }
         {  // ln rho and u of plane z' at the column, from the flow region
             const LP<T> *F = cf0 + JD * C::FREG;
