@@ -217,7 +217,10 @@ const char *mhd_last_error(void);
 mhd_status mhd_forcing_draw(double kf, double f0, double sigma, uint64_t seed, int64_t n,
                             mhd_forcing *out);
 
-/* Number of compiled tile shapes, and shape i as "TXxTYxTZ/cz". */
+/* Number of compiled tile shapes, and shape i as "TXxTYxTZ/cz" (box tiles, with
+ * "+ring" for the direct-to-LDS ring kernel and "+march" for the marching-slab kernel)
+ * or "TXxTY+zm" (z-marching column tiles; "64x8+zm": FP32 only, substeps 2 and 3 on
+ * 64x8 tiles, the first substep and the diagnostics on 32x8). */
 int32_t mhd_num_tile_shapes(void);
 mhd_status mhd_tile_shape_name(int32_t i, char *buf, size_t len);
 
@@ -225,8 +228,8 @@ mhd_status mhd_tile_shape_name(int32_t i, char *buf, size_t len);
  * same table mhd_autotune writes).  i = -1 removes the pin. */
 mhd_status mhd_set_tile_shape(const mhd_params *p, int32_t i);
 
-/* Tile shape used for runs of this size and precision, as "TXxTYxTZ/cz"
- * (chosen by the autotuner or the default table); writes into buf. */
+/* Tile shape used for runs of this size and precision, in the same form (chosen by
+ * the autotuner or the default table); writes into buf. */
 mhd_status mhd_tile_config(const mhd_params *p, char *buf, size_t len);
 
 /* Tile shape this context's launches use, in the same form (a context of a batch may
@@ -244,10 +247,11 @@ mhd_status mhd_autotune(const mhd_params *p, int reps, void *hip_stream, double 
  * together: each substep of every run is one tile list, launched as one kernel per
  * (precision, tile shape) class.  Runs never wait on each other's data.  Each run
  * takes the tile shape it would take alone (so its state is bit for bit the same),
- * except that when the runs of one precision bring at least 4096 work-groups per
- * substep with the large-grid tile, grids of at most 64^3 take that tile too, unless
- * mhd_autotune pinned a shape for them (their state then matches the run alone to
- * the parity bar, not bit for bit). */
+ * except that when the runs of one precision bring at least 2^22 cells together they
+ * fill the chip, and every run of that precision takes the filled-chip shape (the
+ * z-marching tile where its grid allows it, else the large ring tile) unless
+ * mhd_autotune pinned a shape for it (its state then matches the run alone to the
+ * parity bar, and the run alone on the same pinned shape bit for bit). */
 mhd_status mhd_batch_create(const mhd_params *runs, int32_t n, void *hip_stream,
                             mhd_batch **out);
 mhd_status mhd_batch_destroy(mhd_batch *b);
