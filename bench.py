@@ -431,6 +431,27 @@ def serving(mhd, nruns=240, nsteps=1000, budget_gb=64.0, slots=32, steps_per_tic
                                 step_latency_p50_ms_by_n={str(k): pct(v, 50) for k, v in sorted(lat_by_n.items())}))
 
 
+def attainable_copy_gbs(gib=2.0, reps=5):
+    """Bandwidth of a plain device-to-device copy (torch copy_, read + write bytes) on
+    this GPU: the attainable HBM rate beside the 8 TB/s peak.  Best of `reps`."""
+    import torch
+    nel = int(gib * 2 ** 30) // 4
+    a = torch.ones(nel, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nel * 4 / (best * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -533,6 +554,8 @@ def main():
         log("[bench] 32^3: max e_f " + " ".join(f"{k}:{v:.1e}" for k, v in cfg1["e_f"].items())
             + f"; GPU {cfg1['gpu_wall_s'] * 1e3:.1f} ms, oracle {cfg1['oracle_wall_s'] * 1e3:.0f} ms")
 
+    copy_gbs = attainable_copy_gbs()
+    log(f"[bench] plain 2 GiB device copy: {copy_gbs:.0f} GB/s (read + write)")
     cells = float(args.n) ** 3
     achieved = r64["sub2_gbs"]
     traffic = stored_traffic(8, args.n, r64["tile"])
@@ -567,7 +590,9 @@ def main():
                      "kernel": kernel_name(r64["tile"]) + f" substep 2 (fused RHS + RK3 update), tile {r64['tile']}",
                      "algorithmic_bytes_per_launch": r64["sub2_bytes"],
                      "launch_ms": r64["sub2_ms"],
-                     "all_substeps_gbs": r64["substep_kernel_gbs"]},
+                     "all_substeps_gbs": r64["substep_kernel_gbs"],
+                     "attainable_copy_gbs": copy_gbs,
+                     "frac_of_attainable": achieved / copy_gbs},
         "cpu_baseline": cpu,
         "config1": cfg1,
         "fp32": None if r32 is None else {
