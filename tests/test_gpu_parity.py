@@ -272,8 +272,10 @@ def test_full_size_sampled_one_step(mhd, n, prec, sigma, nu):
     assert np.all(e <= TOL[prec]), e
 
 
-def test_full_size_band_every_cell_fp64(mhd):
-    """512^3 FP64 in the benchmark's launch configuration: one step from a seeded state,
+@pytest.mark.parametrize("prec", [8, 4])
+def test_full_size_band_every_cell(mhd, prec):
+    """512^3 FP64 and FP32 in the benchmark's launch configuration (FP32: substeps 2 and 3
+    on the 64-wide tiles): one step from a seeded state,
     compared on EVERY cell of a 16-plane z-band (4.2 M cells, all x and y, so every tile
     column including the ones that wrap in x, and the band crosses a z-segment boundary
     of the z-marching kernel at z = 256).  The oracle steps a periodic 34-plane slab cut
@@ -282,17 +284,17 @@ def test_full_size_band_every_cell_fp64(mhd):
     band).  The forcing record is the first draw of the schedule with k_z = 0, whose
     forcing does not depend on z, so that the slab sees the same forcing."""
     n, z0, band, halo = 512, 248, 16, 9
-    rp = mi.RunParams(n, n, n, nu=4e-4, eta=4e-4, dt=1e-3, precision=8)
+    rp = mi.RunParams(n, n, n, nu=4e-4, eta=4e-4, dt=1e-3, precision=prec)
     rec = next(r for r in mi.forcing_schedule(0, 200, 3.0, 0.02, 0.0) if r.k[2] == 0)
     print(f"generating {n}^3 state", flush=True)
-    st = mi.noise_state(rp, 23, 0.05, 0.05, 0.05)
+    st = mi.noise_state(rp, 23, 0.05, 0.05, 0.05, dtype=_dtype(prec))
     print("one GPU step", flush=True)
     got, _ = gpu_run(mhd, rp, st, [rec])
     got = got[0]
     print(f"tile config {mhd.mhd_tile_config(mhd.params_from(rp))}; oracle on the slab", flush=True)
     nzs = band + 2 * halo
     planes = [(z0 - halo + j) % n for j in range(nzs)]
-    slab = np.ascontiguousarray(st[:, planes])
+    slab = np.ascontiguousarray(st[:, planes]).astype(np.float64)
     del st
     h = rp.lz / n
     sp = mi.RunParams(n, n, nzs, nu=rp.nu, eta=rp.eta, dt=rp.dt, precision=8, lz=nzs * h)
@@ -300,9 +302,9 @@ def test_full_size_band_every_cell_fp64(mhd):
     want = want[:, halo:halo + band]
     g = got[:, z0:z0 + band]
     e, _ = oracle.tolerance_error(g, want, ts[0], rp.dt)
-    print("512^3 fp64 band of 16 planes, every cell: e_f = " +
+    print(f"512^3 fp{8 * prec} band of 16 planes, every cell: e_f = " +
           " ".join(f"{k}:{x:.2e}" for k, x in zip(mi.FIELD_NAMES, e)), flush=True)
-    assert np.all(e <= TOL[8]), e
+    assert np.all(e <= TOL[prec]), e
 
 
 @pytest.mark.parametrize("n,prec,sigma,nu,checks", [(256, 8, 1.0, 1e-3, (100, 200)),
