@@ -194,8 +194,10 @@ def growth_run(mhd, n=256, steps=200):
         diag = mhd.mhd_get_diag(h)
     finally:
         mhd.mhd_destroy(h)
+    sub2_bytes = 21.0 * 8 * n ** 3
     return dict(steps=steps, ms_per_step=float(np.mean(step_ms)),
                 cell_substeps_per_s=3.0 * n ** 3 / (float(np.mean(step_ms)) * 1e-3),
+                substep2_ms=kms[1], roofline_frac=sub2_bytes / (kms[1] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 lambda_steps_1_200=mhd.mhd_growth_rate(diag, 1, len(diag)),
                 lambda_steps_101_200=mhd.mhd_growth_rate(diag, 101, len(diag)),
                 em_first=diag[0]["em"], em_last=diag[-1]["em"], urms_last=diag[-1]["urms"],
