@@ -19,6 +19,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -54,6 +55,13 @@ struct MultiRunner {
     bool split_by_size = false;
     // captured graphs, keyed by the number of steps of every group
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    // step counts launched once without a graph (capture_on_reuse): captured when seen again
+    std::set<std::vector<int64_t>> seen_once;
+    // false: capture a graph the first time a step count is run (batches: the caller
+    // warms up once and then replays); true: launch directly the first time and capture
+    // only when the same step counts come back (the server, whose set of runs changes
+    // every few ticks: a graph used once costs its capture and instantiation for nothing)
+    bool capture_on_reuse = false;
 
     ~MultiRunner() { clear(); }
 
@@ -61,6 +69,7 @@ struct MultiRunner {
     {
         for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
+        seen_once.clear();
     }
 
     void clear()
@@ -241,6 +250,7 @@ struct MultiRunner {
             if (m < 1 || m > CHUNK) return fail(MHD_E_INVALID, "batch: step counts must lie in [1, CHUNK]");
         mhd_status st = stage(mg);
         if (st != MHD_OK) return st;
+        if (use_graph && capture_on_reuse && !graphs.count(mg) && seen_once.insert(mg).second) use_graph = false;
         if (use_graph) {
             auto it = graphs.find(mg);
             if (it == graphs.end()) {
@@ -621,6 +631,7 @@ mhd_status mhd_server_create(size_t hbm_budget, int32_t max_slots, int32_t steps
     s->max_slots = max_slots;
     s->steps_per_tick = steps_per_tick;
     s->mr.split_by_size = true;
+    s->mr.capture_on_reuse = true;
     mhd_status st = s->mr.init_stream(hip_stream);
     if (st != MHD_OK) {
         delete s;
