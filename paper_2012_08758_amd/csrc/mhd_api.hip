@@ -248,8 +248,25 @@ mhd_status check_forcing(const mhd_forcing &f)
 // exp(i theta), theta = K.x + phi.  From Eqs. forcing, fnorm and feigen:
 // f = Re{N f_k e^{i theta}} = N Re(f_k) cos - N Im(f_k) sin, with
 // Re f_k = K x (K x e) / D and Im f_k = -sigma |K| (K x e) / D.
+// cos and sin of 2 pi m / n, m = 0..n-1 (interleaved): the phases of one axis for any
+// integer wave number are a permutation of this table
+static std::vector<double> unit_circle(int n)
+{
+    std::vector<double> u(2 * (size_t)n);
+    for (int m = 0; m < n; m++) {
+        const double th = 2.0 * M_PI * (double)m / (double)n;
+        u[2 * (size_t)m] = std::cos(th);
+        u[2 * (size_t)m + 1] = std::sin(th);
+    }
+    return u;
+}
+
+// The forcing block of one step: head a, b (f = a cos(theta) + b sin(theta) with theta =
+// k.x + phi), the on-flag, then per axis the (cos, sin) of k_a x_a (x also + phi) at every
+// index, gathered from the axis's unit-circle table (u[a], from unit_circle(n_a)) and, for
+// x, rotated by phi.
 template <typename T>
-static void forcing_block(const mhd_params &p, const mhd_forcing &f, T *blk)
+static void forcing_block(const mhd_params &p, const mhd_forcing &f, T *blk, const std::vector<double> *u)
 {
     constexpr int W = FSLOT<T>;
     for (int i = 0; i < FHEAD; i++) blk[i] = (T)0;
@@ -275,14 +292,16 @@ static void forcing_block(const mhd_params &p, const mhd_forcing &f, T *blk)
     blk[6] = (T)1;
     const int n[3] = {p.nx, p.ny, p.nz};
     T *tab[3] = {Ex, Ey, Ez};
+    const double cp = std::cos(f.phi), sp = std::sin(f.phi);
     for (int a = 0; a < 3; a++) {
         const int64_t na = n[a];
+        const double *U = u[a].data();
         for (int64_t i = 0; i < na; i++) {
             int64_t m = ((int64_t)f.k[a] * i) % na;
             if (m < 0) m += na;
-            const double th = 2.0 * M_PI * (double)m / (double)na + (a == 0 ? f.phi : 0.0);
-            tab[a][W * i] = (T)std::cos(th);
-            tab[a][W * i + 1] = (T)std::sin(th);
+            const double c = U[2 * m], sn = U[2 * m + 1];
+            tab[a][W * i] = (T)(a == 0 ? c * cp - sn * sp : c);
+            tab[a][W * i + 1] = (T)(a == 0 ? sn * cp + c * sp : sn);
         }
     }
 }
@@ -831,6 +850,9 @@ template void fill_desc<double>(const mhd_ctx *, RunDesc<double> &, int, int64_t
 // Write the forcing blocks of steps [n0, n0+m) into host memory dst.
 mhd_status ctx_forcing_blocks(mhd_ctx *c, int64_t n0, int64_t m, void *dst)
 {
+    const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+    for (int a = 0; a < 3; a++)
+        if (c->unit[a].size() != 2 * (size_t)n[a]) c->unit[a] = unit_circle(n[a]);
     for (int64_t s = 0; s < m; s++) {
         mhd_forcing f;
         mhd_status st = ctx_forcing_at(c, n0 + s, f);
@@ -838,9 +860,9 @@ mhd_status ctx_forcing_blocks(mhd_ctx *c, int64_t n0, int64_t m, void *dst)
         st = check_forcing(f);
         if (st != MHD_OK) return st;
         if (c->p.precision == MHD_FP64)
-            forcing_block<double>(c->p, f, (double *)dst + (size_t)s * c->fstride);
+            forcing_block<double>(c->p, f, (double *)dst + (size_t)s * c->fstride, c->unit);
         else
-            forcing_block<float>(c->p, f, (float *)dst + (size_t)s * c->fstride);
+            forcing_block<float>(c->p, f, (float *)dst + (size_t)s * c->fstride, c->unit);
     }
     return MHD_OK;
 }

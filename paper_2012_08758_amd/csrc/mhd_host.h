@@ -87,6 +87,7 @@ struct mhd_ctx {
     int64_t rcount = 0;      // records written on the device since the last drain
     double clock_hz = 1e8;   // rate of the device wall clock in the records
     std::vector<mhd_diag> host_diag;
+    std::vector<double> unit[3];   // cos, sin of 2 pi m / n per axis (forcing phase tables)
     // magnetic spectrum workspace (allocated by the first mhd_spectrum call)
     void *spec_ws = nullptr;
     size_t spec_bytes = 0;
