@@ -156,7 +156,13 @@ static void fill_coef(const mhd_params &p, Coef<T> &c, DCoef &dc)
         for (int k = 0; k < 3; k++) c.w1[a][k] = (T)(w1[k] / h[a]);
         for (int k = 0; k < 4; k++) c.w2[a][k] = (T)(w2[k] / (h[a] * h[a]));
     }
-    for (int k = 0; k < 3; k++) c.wm[k] = (T)(w2[k + 1] / (4.0 * h[0] * h[1]));
+    for (int role = 0; role < 2; role++) {
+        const double f = role == 0 ? p.nu / 3.0 : 1.0;
+        for (int k = 0; k < 3; k++) {
+            c.wm[role][k] = (T)(f * w2[k + 1] / (4.0 * h[0] * h[1]));
+            for (int a = 0; a < 2; a++) c.wq[role][a][k] = (T)(f * w2[k + 1] / (4.0 * h[a] * h[2]));
+        }
+    }
     for (int s = 0; s < 3; s++) {
         c.bdt[s] = (T)(RK_B[s] * p.dt);
         c.brho[s] = s == 0 ? (T)0 : (T)(RK_B[s] * RK_A[s] / RK_B[s - 1]);

@@ -55,7 +55,10 @@ struct Coef {
     // the same stencil weights scaled by the inverse spacings, x and y (z-marching kernel)
     T w1[2][3];   // W1_s / h_axis, s = 1..3
     T w2[2][4];   // W2_s / h_axis^2, s = 0..3
-    T wm[3];      // W2_s / (4 h_x h_y), s = 1..3 (diagonal x-y derivative)
+    // per thread role of that kernel (0: ln rho and u, whose mixed derivatives enter
+    // the viscous term with nu / 3; 1: A, whose enter the current density as they are)
+    T wm[2][3];     // diagonal x-y derivative: W2_s / (4 h_x h_y), s = 1..3
+    T wq[2][2][3];  // diagonal x-z, y-z derivatives: W2_s / (4 h_a h_z), a = x, y
 };
 
 struct DCoef {      // FP64 inverse spacings and mean field, for the diagnostics

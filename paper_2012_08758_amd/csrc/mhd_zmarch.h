@@ -51,8 +51,14 @@ struct ZmCfg {
     static constexpr int FLOW = 0;                         // D flow regions
     static constexpr int FIELD = FLOW + D * FREG;          // D field regions
     static constexpr int S2 = FIELD + D * AREG;            // D s-2 regions (+ forcing z slot)
-    static constexpr int XJ = S2 + D * SREG;               // exchange: rho^-1 J x B + f [3][NC]
-    static constexpr int FH = XJ + 3 * NC;                 // forcing head and the tile's x, y phase slots
+    // FP32: the exchange of a step is consumed one step later (two slots, by step
+    // parity), so that a step holds one barrier; FP64 keeps a barrier of its own for it
+    // (512^3 substeps, FP32: 10.3 -> 9.7 ms per step; FP64 with the deferral: 5.9 ->
+    // 6.2 ms for substep 2, so not there)
+    static constexpr bool DEFER = sizeof(T) == 4;
+    static constexpr int NXJ = DEFER ? 2 : 1;
+    static constexpr int XJ = S2 + D * SREG;               // exchange: rho^-1 J x B + f [NXJ][3][NC]
+    static constexpr int FH = XJ + NXJ * 3 * NC;           // forcing head and the tile's x, y phase slots
     static constexpr int NFH = FHEAD / EPL + TX + TY;
     static constexpr int NFHC = (NFH + 63) / 64;           // wave-copies of the forcing slots
     static constexpr int LDS = FH + NFHC * 64 * EPL;
@@ -86,10 +92,21 @@ __device__ __forceinline__ auto ldv(const PT *p)
         return *p;
 }
 
-// Folded stencil weights for the pushes of the mixed derivatives.
-template <typename T>
-struct ZmW {
-    T kxz[3], kyz[3];     // ihm_xz W2_s, ihm_yz W2_s (s = 1..3)
+// One field's plane box in LDS, addressed relative to this thread's column (offsets
+// -CO .. CO, CO = 3 rows + 3 columns).  FP32 reads go through two opaque bases, the box
+// origin for negative offsets and the column for the others, so that every pair the
+// compiler merges into ds_read2_b32 (two 8-bit dword offsets from one base) finds its
+// base among these two: without them it adds a fresh base per pair (about 25 extra
+// integer operations per plane, 4 % of the substep's VALU work).  FP64 reads stay one
+// by one at 16-bit offsets from the step's single base.
+template <typename T, int CO>
+struct Box {
+    const LP<T> *lo, *hi;
+    __device__ __forceinline__ explicit Box(const LP<T> *col) : lo(col - CO), hi(col)
+    {
+        if constexpr (sizeof(T) == 4) asm volatile("" : "+v"(lo), "+v"(hi));
+    }
+    __device__ __forceinline__ T operator[](int o) const { return o < 0 ? ldv(lo + (o + CO)) : ldv(hi + o); }
 };
 
 // wait until at most N vector-memory operations of this wave are outstanding
@@ -117,13 +134,13 @@ __device__ __forceinline__ void zm_wait(int key)
 template <typename T>
 struct Pairs {
     T c, p[3], d[3];
-    template <class PT>
-    __device__ __forceinline__ void load(const PT *s, int st)
+    template <class B>
+    __device__ __forceinline__ void load(const B &s, int st)
     {
-        c = ldv(s);
+        c = s[0];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            const T a = ldv(s + (k + 1) * st), b = ldv(s - (k + 1) * st);
+            const T a = s[(k + 1) * st], b = s[-(k + 1) * st];
             p[k] = a + b;
             d[k] = a - b;
         }
@@ -139,30 +156,33 @@ struct Pairs {
     __device__ __forceinline__ T d6() const { return T(-20) * c + T(15) * p[0] + T(-6) * p[1] + p[2]; }
 };
 
-// d_x d_y from the two diagonals through s[0] (rows of stride sy); w = the diagonal
-// weights divided by 4 h_x h_y
-template <typename T, class PT>
-__device__ __forceinline__ T zm_dxy(const PT *s, int sy, const T (&w)[3])
+// acc + d_x d_y from the two diagonals through s[0] (rows of stride sy); w = the
+// diagonal weights divided by 4 h_x h_y (times the role's factor)
+template <typename T, class B>
+__device__ __forceinline__ T zm_dxy(T acc, const B &s, int sy, const T (&w)[3])
 {
     const int p = 1 + sy, q = 1 - sy;
-    return w[0] * ((ldv(s + p) + ldv(s - p)) - (ldv(s + q) + ldv(s - q))) +
-           w[1] * ((ldv(s + 2 * p) + ldv(s - 2 * p)) - (ldv(s + 2 * q) + ldv(s - 2 * q))) +
-           w[2] * ((ldv(s + 3 * p) + ldv(s - 3 * p)) - (ldv(s + 3 * q) + ldv(s - 3 * q)));
+#pragma unroll
+    for (int k = 1; k <= 3; k++) acc = fma(w[k - 1], (s[k * p] + s[-k * p]) - (s[k * q] + s[-k * q]), acc);
+    return acc;
 }
 
 // in-plane stencil weights divided by the spacings, read once and pinned in scalar
-// registers
+// registers; the mixed-derivative weights are those of the thread's role (the flow
+// role's carry the nu / 3 of the viscous term)
 template <typename T>
 struct ZmWts {
-    T w1x[3], w1y[3], w2x[4], w2y[4], wm[3];
-    __device__ __forceinline__ void load(const Coef<T> &c)
+    T w1x[3], w1y[3], w2x[4], w2y[4], wm[3], qx[3], qy[3];
+    __device__ __forceinline__ void load(const Coef<T> &c, int role)
     {
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             w1x[k] = c.w1[0][k];
             w1y[k] = c.w1[1][k];
-            wm[k] = c.wm[k];
-            asm volatile("" : "+s"(w1x[k]), "+s"(w1y[k]), "+s"(wm[k]));
+            wm[k] = c.wm[role][k];
+            qx[k] = c.wq[role][0][k];
+            qy[k] = c.wq[role][1][k];
+            asm volatile("" : "+s"(w1x[k]), "+s"(w1y[k]), "+s"(wm[k]), "+s"(qx[k]), "+s"(qy[k]));
         }
 #pragma unroll
         for (int k = 0; k < 4; k++) {
@@ -229,14 +249,15 @@ struct PS {
 // output plane and is added before it is finished; the s = 3 '-' part starts the
 // accumulator of plane z' + 3, which takes over the slot the output just released, so
 // it is subtracted there; the caller cleared that slot after the output.
+// q_s = w_s d_s: one fused multiply-add per target plane.
 template <typename T, int J>
-__device__ __forceinline__ void push3(T (&acc)[6], T q1, T q2, T q3)
+__device__ __forceinline__ void push3(T (&acc)[6], const T (&d)[3], const T (&w)[3])
 {
-    acc[PS<J, -1>::v] += q1;
-    acc[PS<J, 1>::v] -= q1;
-    acc[PS<J, -2>::v] += q2;
-    acc[PS<J, 2>::v] -= q2;
-    acc[PS<J, 3>::v] -= q3;
+    acc[PS<J, -1>::v] = fma(w[0], d[0], acc[PS<J, -1>::v]);
+    acc[PS<J, 1>::v] = fma(-w[0], d[0], acc[PS<J, 1>::v]);
+    acc[PS<J, -2>::v] = fma(w[1], d[1], acc[PS<J, -2>::v]);
+    acc[PS<J, 2>::v] = fma(-w[1], d[1], acc[PS<J, 2>::v]);
+    acc[PS<J, 3>::v] = fma(-w[2], d[2], acc[PS<J, 3>::v]);
 }
 
 template <typename T, int SUB, bool DIAG, bool STORE, bool UPW, int TXV>
@@ -255,9 +276,9 @@ template <typename T>
 struct ZmK {
     T bdt, brho, bext[3];
     ZmWts<T> w;
-    __device__ __forceinline__ void load(const Coef<T> &c, int sub)
+    __device__ __forceinline__ void load(const Coef<T> &c, int sub, int role)
     {
-        w.load(c);
+        w.load(c, role);
         bdt = c.bdt[sub];
         brho = c.brho[sub];
 #pragma unroll
@@ -284,6 +305,8 @@ struct ZmState {
     T acc[3][6];
     T del[10][3];
     T fpr, fpi;       // field: forcing exp(i (k_x x + k_y y)) at the column
+    T pend[3];        // flow, deferred exchange: the last output plane's new u, still without
+                      // dt beta rho^-1 J x B + f
     double dg[9];     // diagnostics in the order of the per-tile partials: |B|^2, |u|^2, rho |u|^2,
                       // ln rho, B_x, B_y, B_z, max |u|^2, non-finite cells; a flow thread sums the
                       // u and ln rho terms, a field thread the B terms and the non-finite count
@@ -292,8 +315,8 @@ struct ZmState {
 };
 
 // first derivative in FP64 of FP32 values in LDS (diagnostics of FP32 runs)
-template <class PT>
-__device__ __forceinline__ double zm_d1d(const PT *s, int st, double ih)
+template <class B>
+__device__ __forceinline__ double zm_d1d(const B &s, int st, double ih)
 {
     return ih * (W1_1 * ((double)s[st] - (double)s[-st]) + W1_2 * ((double)s[2 * st] - (double)s[-2 * st]) +
                  W1_3 * ((double)s[3 * st] - (double)s[-3 * st]));
@@ -303,11 +326,21 @@ __device__ __forceinline__ double zm_d1d(const PT *s, int st, double ih)
 // One step of the march: wait for the newest plane z' (step k), request the plane two
 // steps ahead, finish the output plane z' - 3 (k >= 6), then fold plane z' into the
 // register queues and pending accumulators.  J = k mod 6 fixes every queue slot;
+// Complete a flow thread's pending output plane: add dt beta (rho^-1 J x B + f), which
+// the field thread of the column left in exchange slot xp, and store u.
+template <typename T, int NC>
+__device__ __forceinline__ void zm_flush(const T (&pend)[3], const LP<T> *xp, const RunDesc<T> &r, int out_set,
+                                         uint64_t zb, uint32_t gcb, T bdt)
+{
+#pragma unroll
+    for (int m = 0; m < 3; m++) *(G<T> *)((G<char> *)r.buf[out_set][1 + m] + zb + gcb) = pend[m] + bdt * xp[m * NC];
+}
+
 // ROLE 0 is a flow thread, 1 a field thread.
 template <typename T, int SUB, bool DIAG, bool STORE, bool UPW, int TXV, int ROLE, int J, class KR, class ISSUE>
 __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, const KR &Kr, const ZmK<T> &Zk,
                                         const DCoef &dc, const RunDesc<T> &r, LP<T> *&pb0, LP<T> *&sb0, LP<T> *&xb0, LP<T> *&cf0, int col,
-                                        uint64_t gcol, uint64_t plane_b, int zs, int out_set, T (&fa)[3], T (&fb)[3],
+                                        uint32_t gcb, uint64_t plane_b, int zs, int out_set, T (&fa)[3], T (&fb)[3],
                                         bool &fon, ISSUE &issue)
 {
     using C = ZmCfg<T, TXV>;
@@ -323,7 +356,7 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
     // this thread's planes (pb0 points 3 rows and 3 columns before its column in slot 0
     // of its role's region), s-2 values and exchange slots; the asm keeps the compiler
     // from hoisting addresses derived from them out of the step loop
-    asm volatile("" : "+v"(pb0), "+v"(sb0), "+v"(xb0), "+v"(cf0));
+    asm volatile("" : "+v"(pb0), "+v"(sb0), "+v"(xb0), "+v"(cf0), "+v"(gcb));
     constexpr int CO = 3 * XW + 3;
     const LP<T> *P = pb0 + JD * (ROLE == 0 ? C::FREG : C::AREG) + CO;  // P[f * PLE] = field f of the role at the column
     const LP<T> *S2 = sb0 + JD * C::SREG;                               // S2[f * NC] = s-2 value of field f
@@ -347,35 +380,41 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
     // ---------------------------------------------------------------- output plane
     // the newest plane's centre values and the s = 3 differences that complete it
     T now[4];
+    // the role's fields in this step's slot (flow: ln rho, u_x, u_y, u_z; field: A)
+    using Bx = Box<T, CO>;
+    const Bx F0(P), F1(P + PLE), F2(P + 2 * PLE), F3(P + (ROLE == 0 ? 3 : 2) * PLE);
     if constexpr (ROLE == 0) {
-        const LP<T> *L0 = P, *X = P + PLE, *Y = P + 2 * PLE, *W = P + 3 * PLE;
-        now[0] = ldv(L0);
-        now[1] = ldv(X);
-        now[2] = ldv(Y);
-        now[3] = ldv(W);
+        const Bx &X = F1, &Y = F2, &W = F3;
+        now[0] = F0[0];
+        now[1] = X[0];
+        now[2] = Y[0];
+        now[3] = W[0];
         if constexpr (STORE) {
-            const T k3x = Kr.nu3 * Kr.ihm[1] * T(W2_3), k3y = Kr.nu3 * Kr.ihm[2] * T(W2_3);
-            S.acc[0][PO] += k3x * (ldv(W + 3) - ldv(W - 3));
-            S.acc[1][PO] += k3y * (ldv(W + 3 * XW) - ldv(W - 3 * XW));
-            S.acc[2][PO] += k3x * (ldv(X + 3) - ldv(X - 3)) + k3y * (ldv(Y + 3 * XW) - ldv(Y - 3 * XW));
+            const T k3x = Zk.w.qx[2], k3y = Zk.w.qy[2];
+            S.acc[0][PO] = fma(k3x, W[3] - W[-3], S.acc[0][PO]);
+            S.acc[1][PO] = fma(k3y, W[3 * XW] - W[-3 * XW], S.acc[1][PO]);
+            S.acc[2][PO] = fma(k3y, Y[3 * XW] - Y[-3 * XW], fma(k3x, X[3] - X[-3], S.acc[2][PO]));
         }
     } else {
-        const LP<T> *AX = P, *AY = P + PLE, *AZ = P + 2 * PLE;
-        now[0] = ldv(AX);
-        now[1] = ldv(AY);
-        now[2] = ldv(AZ);
+        const Bx &AX = F0, &AY = F1, &AZ = F2;
+        now[0] = AX[0];
+        now[1] = AY[0];
+        now[2] = AZ[0];
         now[3] = T(0);
         if constexpr (STORE) {
-            const T k3x = Kr.ihm[1] * T(W2_3), k3y = Kr.ihm[2] * T(W2_3);
-            S.acc[0][PO] += k3x * (ldv(AZ + 3) - ldv(AZ - 3));
-            S.acc[1][PO] += k3y * (ldv(AZ + 3 * XW) - ldv(AZ - 3 * XW));
-            S.acc[2][PO] += k3x * (ldv(AX + 3) - ldv(AX - 3)) + k3y * (ldv(AY + 3 * XW) - ldv(AY - 3 * XW));
+            const T k3x = Zk.w.qx[2], k3y = Zk.w.qy[2];
+            S.acc[0][PO] = fma(k3x, AZ[3] - AZ[-3], S.acc[0][PO]);
+            S.acc[1][PO] = fma(k3y, AZ[3 * XW] - AZ[-3 * XW], S.acc[1][PO]);
+            S.acc[2][PO] = fma(k3y, AY[3 * XW] - AY[-3 * XW], fma(k3x, AX[3] - AX[-3], S.acc[2][PO]));
         }
     }
 
     // The field thread of a column forms rho^-1 J x B + f (it holds ln rho and u of the
-    // output plane, see del) and hands it to the flow thread through LDS.
-    LP<T> *XJ = xb0;  // XJ[m * NC]: component m at the column
+    // output plane, see del) and hands it to the flow thread through LDS.  Deferred
+    // (C::DEFER): in the slot of this step's parity, and the flow thread completes that
+    // plane's u one step later, after the barrier that opens the next step; otherwise
+    // behind a barrier of this step.
+    LP<T> *XJ = xb0 + (C::DEFER ? (J & 1) * 3 * NC : 0);  // XJ[m * NC]: component m at the column
     if (out) {
         const T ihz = Kr.ih1[2], ih2z = Kr.ih2[2];
         if constexpr (ROLE == 0) {
@@ -402,23 +441,33 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 R[2] = S.acc[1][PO] + nu * Y.d2(ih2z) - uz * dzy + nu * (dzy * gz + dyz * gz) - n23 * dzz * gy;
                 R[3] = S.acc[2][PO] + (nu + Kr.nu3) * W.d2(ih2z) - uz * dzz +
                        nu * (T(2) * dzz * gz + dzx * gx + dzy * gy) - n23 * (divxy + dzz) * gz - Kr.cs2 * gz;
-                lds_barrier();  // rho^-1 J x B + f of the column is in XJ
-                R[1] += XJ[0];
-                R[2] += XJ[NC];
-                R[3] += XJ[2 * NC];
                 const T bdt = Zk.bdt, brho = Zk.brho;
+                if constexpr (C::DEFER) {
+                    if (k >= 7)  // the previous step's output plane, with its exchange
+                        zm_flush<T, NC>(S.pend, xb0 + ((J + 1) & 1) * 3 * NC, r, out_set, (uint64_t)(zo - 1) * plane_b,
+                                        gcb, bdt);
+                } else {
+                    lds_barrier();  // rho^-1 J x B + f of the column is in XJ
+                    R[1] += XJ[0];
+                    R[2] += XJ[NC];
+                    R[3] += XJ[2 * NC];
+                }
                 const T v[4] = {l0, ux, uy, uz};
-                const uint64_t g = gcol + (uint64_t)zo * (plane_b / sizeof(T));
+                T o[4];
 #pragma unroll
                 for (int f = 0; f < 4; f++) {
-                    T o;
                     if constexpr (SUB == 0) {
-                        o = v[f] + bdt * R[f];
+                        o[f] = v[f] + bdt * R[f];
                     } else {
                         const T old = S2[f * NC];
-                        o = v[f] + brho * (v[f] - old) + bdt * R[f];
+                        o[f] = v[f] + brho * (v[f] - old) + bdt * R[f];
                     }
-                    ((G<T> *)r.buf[out_set][f])[g] = o;
+                }
+                const uint64_t zb = (uint64_t)zo * plane_b;
+#pragma unroll
+                for (int f = 0; f < 4; f++) {
+                    if (C::DEFER && f > 0) S.pend[f - 1] = o[f];
+                    else *(G<T> *)((G<char> *)r.buf[out_set][f] + zb + gcb) = o[f];
                 }
             }
         } else {
@@ -449,7 +498,7 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 R[1] = S.del[4][JD] + eta * AY.d2(ih2z) + (uz * bx - ux * bz);
                 R[2] = S.del[5][JD] + eta * AZ.d2(ih2z) + (ux * by - uy * bx);
                 const T bdt = Zk.bdt, brho = Zk.brho;
-                const uint64_t g = gcol + (uint64_t)zo * (plane_b / sizeof(T));
+                const uint64_t zb = (uint64_t)zo * plane_b;
 #pragma unroll
                 for (int m = 0; m < 3; m++) {
                     const T vv = m == 0 ? AX.v[3] : (m == 1 ? AY.v[3] : AZ.v[3]);
@@ -460,7 +509,7 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                         const T old = S2[(4 + m) * NC];
                         o = vv + brho * (vv - old) + bdt * R[m];
                     }
-                    ((G<T> *)r.buf[out_set][4 + m])[g] = o;
+                    *(G<T> *)((G<char> *)r.buf[out_set][4 + m] + zb + gcb) = o;
                 }
             }
             if constexpr (DIAG) {
@@ -482,7 +531,7 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                                 finite_v(AY.v[3]) && finite_v(AZ.v[3]);
                 S.dg[8] += ok ? 0.0 : 1.0;
             }
-            if constexpr (STORE) lds_barrier();  // XJ written
+            if constexpr (STORE && !C::DEFER) lds_barrier();  // XJ written
         }
     }
 
@@ -496,10 +545,9 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
     // its in-plane derivatives, which go straight into the accumulators, and its x- or
     // y-differences, pushed as mixed x-z / y-z derivatives into the planes z' +- s.
     if constexpr (ROLE == 0) {
-        const LP<T> *L0 = P, *X = P + PLE, *Y = P + 2 * PLE, *W = P + 3 * PLE;
+        const Bx &L0 = F0, &X = F1, &Y = F2, &W = F3;
         if constexpr (STORE) {
             const T nu = Kr.nu, nu3 = Kr.nu3, n23 = Kr.nu2_3;
-            const T kx = nu3 * Kr.ihm[1], ky = nu3 * Kr.ihm[2];
             const T ux = now[1], uy = now[2];
             T gx, gy, pl;
             {
@@ -522,8 +570,8 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 const T d2xx = a.d2w(Zk.w.w2x), d2yx = b.d2w(Zk.w.w2y);
                 S.acc[0][PN] += nu * (d2xx + d2yx) + nu3 * d2xx - (ux * dxx + uy * dyx) + nu * (T(2) * dxx * gx + dyx * gy) -
                                 Kr.cs2 * gx;
-                S.acc[1][PN] += nu3 * zm_dxy(X, XW, Zk.w.wm);
-                push3<T, J>(S.acc[2], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
+                S.acc[1][PN] = zm_dxy(S.acc[1][PN], X, XW, Zk.w.wm);
+                push3<T, J>(S.acc[2], a.d, Zk.w.qx);
             }
             // u_y
             T dyy;
@@ -536,8 +584,8 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 const T d2xy = a.d2w(Zk.w.w2x), d2yy = b.d2w(Zk.w.w2y);
                 S.acc[1][PN] += nu * (d2xy + d2yy) + nu3 * d2yy - (ux * dxy + uy * dyy) + nu * (dxy * gx + T(2) * dyy * gy) +
                                 nu * dyx * gx - Kr.cs2 * gy;
-                S.acc[0][PN] += nu * dxy * gy + nu3 * zm_dxy(Y, XW, Zk.w.wm);
-                push3<T, J>(S.acc[2], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
+                S.acc[0][PN] = zm_dxy(S.acc[0][PN] + nu * dxy * gy, Y, XW, Zk.w.wm);
+                push3<T, J>(S.acc[2], b.d, Zk.w.qy);
             }
             const T divxy = dxx + dyy;
             S.acc[0][PN] -= n23 * divxy * gx;
@@ -550,8 +598,8 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 b.load(W, XW);
                 const T dxz = a.d1w(Zk.w.w1x), dyz = b.d1w(Zk.w.w1y);
                 S.acc[2][PN] += nu * (a.d2w(Zk.w.w2x) + b.d2w(Zk.w.w2y)) - (ux * dxz + uy * dyz) + nu * (dxz * gx + dyz * gy);
-                push3<T, J>(S.acc[0], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
-                push3<T, J>(S.acc[1], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
+                push3<T, J>(S.acc[0], a.d, Zk.w.qx);
+                push3<T, J>(S.acc[1], b.d, Zk.w.qy);
                 S.del[2][JD] = dxz;
                 S.del[3][JD] = dyz;
             }
@@ -563,10 +611,9 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
 #pragma unroll
         for (int f = 0; f < 4; f++) S.q[f][J] = now[f];
     } else {
-        const LP<T> *AX = P, *AY = P + PLE, *AZ = P + 2 * PLE;
+        const Bx &AX = F0, &AY = F1, &AZ = F2;
         if constexpr (STORE) {
             const T eta = Kr.eta;
-            const T kx = Kr.ihm[1], ky = Kr.ihm[2];
             T dyax;
             {  // A_x: j_x -= D2y A_x, j_y += D_xy A_x, j_z += D_xz A_x (push), B_z -= d_y A_x
                 Pairs<T> a, b;
@@ -575,9 +622,9 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 const T d2x = a.d2w(Zk.w.w2x), d2y = b.d2w(Zk.w.w2y);
                 dyax = b.d1w(Zk.w.w1y);
                 S.acc[0][PN] -= d2y;
-                S.acc[1][PN] += zm_dxy(AX, XW, Zk.w.wm);
+                S.acc[1][PN] = zm_dxy(S.acc[1][PN], AX, XW, Zk.w.wm);
                 S.del[3][JD] = eta * (d2x + d2y);
-                push3<T, J>(S.acc[2], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
+                push3<T, J>(S.acc[2], a.d, Zk.w.qx);
             }
             {  // A_y: j_y -= D2x A_y, j_x += D_xy A_y, j_z += D_yz A_y (push), B_z += d_x A_y
                 Pairs<T> a, b;
@@ -586,9 +633,9 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 const T d2x = a.d2w(Zk.w.w2x), d2y = b.d2w(Zk.w.w2y);
                 S.del[2][JD] = a.d1w(Zk.w.w1x) - dyax;
                 S.acc[1][PN] -= d2x;
-                S.acc[0][PN] += zm_dxy(AY, XW, Zk.w.wm);
+                S.acc[0][PN] = zm_dxy(S.acc[0][PN], AY, XW, Zk.w.wm);
                 S.del[4][JD] = eta * (d2x + d2y);
-                push3<T, J>(S.acc[2], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
+                push3<T, J>(S.acc[2], b.d, Zk.w.qy);
             }
             {  // A_z: j_z -= D2x A_z + D2y A_z, j_x += D_xz A_z, j_y += D_yz A_z (pushes), B_x, B_y
                 Pairs<T> a, b;
@@ -599,8 +646,8 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                 S.del[0][JD] = b.d1w(Zk.w.w1y);
                 S.del[1][JD] = -a.d1w(Zk.w.w1x);
                 S.del[5][JD] = eta * (d2x + d2y);
-                push3<T, J>(S.acc[0], kx * T(W2_1) * a.d[0], kx * T(W2_2) * a.d[1], kx * T(W2_3) * a.d[2]);
-                push3<T, J>(S.acc[1], ky * T(W2_1) * b.d[0], ky * T(W2_2) * b.d[1], ky * T(W2_3) * b.d[2]);
+                push3<T, J>(S.acc[0], a.d, Zk.w.qx);
+                push3<T, J>(S.acc[1], b.d, Zk.w.qy);
             }
         } else {
             // diagnostics only: the B parts of this plane
@@ -695,8 +742,10 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
         const int gx = (x0s + x) % nx;
         sp[j] = (const G<char> *)r.buf[out_set][f] + ((uint64_t)gx + (uint64_t)nx * (y0 + y)) * sizeof(T);
     }
-    // this thread's column and its output address in a plane
-    const uint64_t gcol = (uint64_t)((x0s + cx) % nx) + (uint64_t)nx * (uint64_t)(y0 + cy);
+    // this thread's column: its byte offset in a plane (a plane holds fewer than 2^29
+    // cells, since a run has fewer than 2^32 and nz >= 8), so that the stores take a
+    // scalar base (field + plane) and this one 32-bit offset
+    const uint32_t gcb = (uint32_t)(((uint64_t)((x0s + cx) % nx) + (uint64_t)nx * (uint64_t)(y0 + cy)) * sizeof(T));
     LP<T> *const lb = (LP<T> *)lds;
     LP<T> *pb0 = lb + (flow ? C::FLOW : C::FIELD) + (cy + 3) * XW + cx + 4 - (3 * XW + 3);
     LP<T> *sb0 = lb + C::S2 + col;
@@ -706,7 +755,7 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
     KRegsFor<T, UPW> Kr;
     Kr.load(r.c);
     ZmK<T> Zk;
-    Zk.load(r.c, SUB);
+    Zk.load(r.c, SUB, flow ? 0 : 1);
     const DCoef &dc = r.dc;
 
     auto issue = [&](int k, int d) {
@@ -714,7 +763,9 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
         zp += zp < 0 ? nz : 0;
         zp -= zp >= nz ? nz : 0;
         const int zo = k >= 6 ? zs + k - 6 : zs;
-        const uint64_t zoff = (uint64_t)zp * plane_b;
+        // the plane offsets in scalar registers: one 64-bit add per copy
+        uint64_t zoff = (uint64_t)zp * plane_b, zob = (uint64_t)zo * plane_b;
+        asm volatile("" : "+s"(zoff), "+s"(zob));
 #pragma unroll
         for (int j = 0; j < C::NLP; j++) {
             const int dd = pdst[j] + d * (pdst[j] >= C::FIELD ? C::AREG : C::FREG);
@@ -723,7 +774,7 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
         const G<char> *fzp = (const G<char> *)(fz + EPL * zo);
 #pragma unroll
         for (int j = 0; j < Z::NLS_E; j++) {
-            const G<char> *src = spf[j] ? fzp : sp[j] + (uint64_t)zo * plane_b;
+            const G<char> *src = spf[j] ? fzp : sp[j] + zob;
             __builtin_amdgcn_global_load_lds((gconst_void_t *)src,
                                              (lds_void_t *)(lds + C::S2 + d * C::SREG + (j * NT + wave * 64) * EPL), 16,
                                              0, 0);
@@ -764,17 +815,17 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
     const int nit = (K + 5) / 6;
 #define ZM_STEPS(ROLE)                                                                                               \
     for (int it = 0; it < nit; it++) {                                                                               \
-        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 0>(it * 6 + 0, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 0>(it * 6 + 0, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcb, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 1>(it * 6 + 1, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 1>(it * 6 + 1, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcb, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 2>(it * 6 + 2, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 2>(it * 6 + 2, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcb, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 3>(it * 6 + 3, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 3>(it * 6 + 3, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcb, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 4>(it * 6 + 4, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 4>(it * 6 + 4, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcb, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
-        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 5>(it * 6 + 5, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcol, plane_b, zs,  \
+        zm_body<T, SUB, DIAG, STORE, UPW, TXV, ROLE, 5>(it * 6 + 5, K, lds, S, Kr, Zk, dc, r, pb0, sb0, xb0, cf0, col, gcb, plane_b, zs,  \
                                                   out_set, fa, fb, fon, issue);                                       \
     }
     if (flow) {
@@ -783,6 +834,12 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
         ZM_STEPS(1)
     }
 #undef ZM_STEPS
+    if constexpr (STORE && C::DEFER) {  // the last output plane's u takes the last step's exchange
+        lds_barrier();
+        if (flow)
+            zm_flush<T, NC>(S.pend, xb0 + ((K - 1) & 1) * 3 * NC, r, out_set, (uint64_t)(zs + K - 7) * plane_b, gcb,
+                            Zk.bdt);
+    }
 
     if constexpr (DIAG) {
         // per-tile partials: lane sums -> wave (DPP) -> fixed-order sum over waves
