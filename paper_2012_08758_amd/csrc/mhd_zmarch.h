@@ -109,19 +109,19 @@ struct Box {
     __device__ __forceinline__ T operator[](int o) const { return o < 0 ? ldv(lo + (o + CO)) : ldv(hi + o); }
 };
 
-// wait until at most N vector-memory operations of this wave are outstanding
-// (a runtime choice among the counts that occur; the branch is wave-uniform)
-template <int NL, int NS>
-__device__ __forceinline__ void zm_wait(int key)
+// Wait until at most n vector-memory operations of this wave are outstanding (n is
+// wave-uniform; the immediate of s_waitcnt is picked by a switch; any n above 15 waits
+// for all), then for the LDS, then for the work-group.
+__device__ __forceinline__ void zm_wait(int n)
 {
     __builtin_amdgcn_sched_barrier(0);
-    switch (key) {
-    case 0: __builtin_amdgcn_s_waitcnt(0x0070); break;  // vmcnt(0) lgkmcnt(0)
-    case 1: wait_vmcnt<NS>(); break;
-    case 2: wait_vmcnt<2 * NS>(); break;
-    case 3: wait_vmcnt<NL>(); break;
-    case 4: wait_vmcnt<NL + NS>(); break;
-    default: wait_vmcnt<NL + 2 * NS>(); break;
+    switch (n) {
+#define ZM_W(c) \
+    case c: wait_vmcnt<c>(); break;
+        ZM_W(1) ZM_W(2) ZM_W(3) ZM_W(4) ZM_W(5) ZM_W(6) ZM_W(7) ZM_W(8)
+        ZM_W(9) ZM_W(10) ZM_W(11) ZM_W(12) ZM_W(13) ZM_W(14) ZM_W(15)
+#undef ZM_W
+    default: wait_vmcnt<0>(); break;
     }
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
     __builtin_amdgcn_s_barrier();
@@ -267,7 +267,34 @@ struct Zm {
     static constexpr int NL = C::NLP + NLS_E;                         // copies per step per thread
     static constexpr int NSF = STORE ? 4 : 0, NSA = STORE ? 3 : 0;     // stores per output (flow, field)
     static constexpr int FZ = SUB == 0 ? 0 : C::SV * C::EPL;  // forcing z slot within an s-2 region
-    static_assert(NL + 2 * NSF < 64, "vmcnt is a 6-bit counter");
+    static_assert(NL + 2 * NSF <= 15, "the waits of a step cover at most 15 operations");
+    // A field thread issues its copies of a step after its output stores (below) in the
+    // FP32 kernels without diagnostics, which run four waves per SIMD: there all sixteen
+    // waves issuing at once left the last in line (the field waves) about a quarter of
+    // the step behind (512^3 substep 2: 3.22 -> 2.66 ms).  With two waves per SIMD (FP64,
+    // the diagnostics substep) the early issue measured faster.
+    static constexpr bool LATE = sizeof(T) == 4 && !DIAG;
+    // stores of a thread at step j (output plane j - 6; a flow thread with the deferred
+    // exchange stores ln rho alone at its first output step and u of the previous plane
+    // with every later one)
+    template <int ROLE>
+    __device__ __forceinline__ static int stores(int j)
+    {
+        if (j < 6) return 0;
+        if (ROLE == 0) return (C::DEFER && j == 6) ? (STORE ? 1 : 0) : NSF;
+        return NSA;
+    }
+    // operations a thread issues after the copies of plane k, up to the wait of step k:
+    // in a step a thread issues copies then stores (a field thread with LATE: stores
+    // then copies); plane k's copies are issued at step k - 2 (planes 0 and 1 before the
+    // loop)
+    template <int ROLE>
+    __device__ __forceinline__ static int after(int k, int K)
+    {
+        const int next = k + 1 < K ? NL : 0;
+        if (ROLE == 1 && LATE) return next + stores<1>(k - 1);
+        return stores<ROLE>(k - 2) + next + stores<ROLE>(k - 1);
+    }
 };
 
 // substep constants of the update and the imposed field, read once and pinned in
@@ -350,9 +377,10 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
     constexpr int PO = PS<J, -3>::v;                // pending slot of the output plane (= J)
     constexpr int PN = PS<J, 0>::v;                 // pending slot of plane z' itself
     if (k >= K) return;
-    const int key = 3 * (k + 1 < K ? 1 : 0) + ((STORE && k - 1 >= 6) ? 1 : 0) + ((STORE && k - 2 >= 6) ? 1 : 0);
-    zm_wait<Z::NL, ROLE == 0 ? Z::NSF : Z::NSA>(key);
-    if (k + 2 < K) issue(k + 2, (J + 2) % 3);
+    zm_wait(Z::template after<ROLE>(k, K));
+    // the copies of plane k + 2, into the slot plane k - 1 left (see Zm::LATE)
+    constexpr bool LATE = ROLE == 1 && Z::LATE;
+    if (!LATE && k + 2 < K) issue(k + 2, (J + 2) % 3);
     // this thread's planes (pb0 points 3 rows and 3 columns before its column in slot 0
     // of its role's region), s-2 values and exchange slots; the asm keeps the compiler
     // from hoisting addresses derived from them out of the step loop
@@ -534,6 +562,8 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
             if constexpr (STORE && !C::DEFER) lds_barrier();  // XJ written
         }
     }
+
+    if (LATE && k + 2 < K) issue(k + 2, (J + 2) % 3);
 
     // ---------------------------------------------------------------- fold in plane z'
     // The output plane's slots are free now: they start the accumulators of plane z' + 3.
