@@ -278,7 +278,7 @@ struct Zm {
     // exchange stores ln rho alone at its first output step and u of the previous plane
     // with every later one)
     template <int ROLE>
-    __device__ __forceinline__ static int stores(int j)
+    __host__ __device__ static constexpr int stores(int j)
     {
         if (j < 6) return 0;
         if (ROLE == 0) return (C::DEFER && j == 6) ? (STORE ? 1 : 0) : NSF;
@@ -289,12 +289,33 @@ struct Zm {
     // then copies); plane k's copies are issued at step k - 2 (planes 0 and 1 before the
     // loop)
     template <int ROLE>
-    __device__ __forceinline__ static int after(int k, int K)
+    __host__ __device__ static constexpr int after(int k, int K)
     {
         const int next = k + 1 < K ? NL : 0;
         if (ROLE == 1 && LATE) return next + stores<1>(k - 1);
         return stores<ROLE>(k - 2) + next + stores<ROLE>(k - 1);
     }
+    // Replays a thread's operations in issue order for every step count K up to KMAX and
+    // checks that after() is, at each step k, the number issued after plane k's copies
+    // and before the wait (checked at compile time below).
+    template <int ROLE>
+    __host__ __device__ static constexpr bool after_exact(int KMAX)
+    {
+        constexpr bool late = ROLE == 1 && LATE;
+        for (int K = 1; K <= KMAX; K++) {
+            int end[64] = {}, issued = 0;  // end[p]: operations issued up to plane p's copies
+            end[0] = issued += NL;
+            if (K > 1) end[1] = issued += NL;
+            for (int k = 0; k < K; k++) {
+                if (issued - end[k] != after<ROLE>(k, K)) return false;
+                if (!late && k + 2 < K) end[k + 2] = issued += NL;
+                issued += stores<ROLE>(k);
+                if (late && k + 2 < K) end[k + 2] = issued += NL;
+            }
+        }
+        return true;
+    }
+    static_assert(after_exact<0>(40) && after_exact<1>(40), "vmcnt accounting of a step");
 };
 
 // substep constants of the update and the imposed field, read once and pinned in
