@@ -269,11 +269,10 @@ struct Zm {
     static constexpr int FZ = SUB == 0 ? 0 : C::SV * C::EPL;  // forcing z slot within an s-2 region
     static_assert(NL + 2 * NSF <= 15, "the waits of a step cover at most 15 operations");
     // A field thread issues its copies of a step after its output stores (below) in the
-    // FP32 kernels without diagnostics, which run four waves per SIMD: there all sixteen
-    // waves issuing at once left the last in line (the field waves) about a quarter of
-    // the step behind (512^3 substep 2: 3.22 -> 2.66 ms).  With two waves per SIMD (FP64,
-    // the diagnostics substep) the early issue measured faster.
-    static constexpr bool LATE = sizeof(T) == 4 && !DIAG;
+    // FP32 kernels: with all waves issuing at once the last in line (the field waves)
+    // fell about a quarter of the step behind (512^3 substep 2: 3.22 -> 2.66 ms; the
+    // diagnostics substep 1 % faster).  FP64 measured faster with the early issue.
+    static constexpr bool LATE = sizeof(T) == 4;
     // stores of a thread at step j (output plane j - 6; a flow thread with the deferred
     // exchange stores ln rho alone at its first output step and u of the previous plane
     // with every later one)
