@@ -32,14 +32,16 @@ constexpr int CHUNK = 512;
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Bytes from one field array to the next in a context's state block.  Fields of at
-// least 4 MiB are spaced by their size plus 260.25 KiB: at the plain size (a power of
+// least 4 MiB are spaced by their size plus 132.25 KiB: at the plain size (a power of
 // two on 2^n grids) the reads of one cell from the fourteen arrays fall at addresses
 // that differ only in high bits, and the substeps of a 512^3 FP64 run measured 5-6 %
-// slower (FP32 about 1 %); pads of 128-768 KiB plus 4.25 KiB all did as well.
+// slower.  The pad matters beyond that (512^3, z-marching kernel): 132.25 and 196.25
+// KiB were the fastest (FP32 substep 2 3 % faster than with 260.25), 68.25 cost FP64
+// 1 %, 396.5 and 516.25 cost FP64 4-6 %.
 inline size_t field_spacing(size_t ncell, int precision)
 {
     const size_t fb = align_up(ncell * (size_t)precision, 256);
-    return fb >= ((size_t)4 << 20) ? fb + (256 + 4) * 1024 + 256 : fb;
+    return fb >= ((size_t)4 << 20) ? fb + (128 + 4) * 1024 + 256 : fb;
 }
 
 mhd_status fail(mhd_status s, const std::string &msg);
