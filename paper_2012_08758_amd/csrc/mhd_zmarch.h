@@ -42,11 +42,18 @@ struct ZmCfg {
     // one step's planes: ln rho and u (read by flow threads) and A (field threads) land
     // in separate regions, whole wave-copies each
     static constexpr int NIF = (4 * PV + 63) / 64, NIA = (3 * PV + 63) / 64;
-    static constexpr int NLP = (NIF + NIA + NW - 1) / NW;  // plane copies per thread per step
+    // FP64: the flow threads issue every copy of a step, the field threads none, so that
+    // the field waves (the longer path to the exchange barrier) start their output at
+    // once while the copies still leave at the top of the step (512^3 FP64: diagnostics
+    // substep 5.10 -> 4.98 ms, step 16.5 -> 16.3 ms; FP32 issues from every wave, the
+    // field waves after their stores, see Zm::LATE)
+    static constexpr bool ALLF = sizeof(T) == 8;
+    static constexpr int NWI = ALLF ? NW / 2 : NW, NTI = 64 * NWI;  // waves, threads that issue copies
+    static constexpr int NLP = (NIF + NIA + NWI - 1) / NWI;  // plane copies per issuing thread per step
     static constexpr int FREG = NIF * 64 * EPL, AREG = NIA * 64 * EPL;  // values per slot
     static constexpr int SV = NF * NC / EPL;               // copies of the s-2 state per step
-    static constexpr int NLS = (SV + 1 + NT - 1) / NT;     // ... plus the forcing z slot
-    static constexpr int SREG = NLS * NT * EPL;
+    static constexpr int NLS = (SV + 1 + NTI - 1) / NTI;   // ... plus the forcing z slot
+    static constexpr int SREG = NLS * NTI * EPL;
     static constexpr int D = 3;                            // slots: planes in flight + the one in use
     static constexpr int FLOW = 0;                         // D flow regions
     static constexpr int FIELD = FLOW + D * FREG;          // D field regions
@@ -110,7 +117,7 @@ struct Box {
 };
 
 // Wait until at most n vector-memory operations of this wave are outstanding (n is
-// wave-uniform; the immediate of s_waitcnt is picked by a switch; any n above 15 waits
+// wave-uniform; the immediate of s_waitcnt is picked by a switch; any n above 31 waits
 // for all), then for the LDS, then for the work-group.
 __device__ __forceinline__ void zm_wait(int n)
 {
@@ -119,7 +126,9 @@ __device__ __forceinline__ void zm_wait(int n)
 #define ZM_W(c) \
     case c: wait_vmcnt<c>(); break;
         ZM_W(1) ZM_W(2) ZM_W(3) ZM_W(4) ZM_W(5) ZM_W(6) ZM_W(7) ZM_W(8)
-        ZM_W(9) ZM_W(10) ZM_W(11) ZM_W(12) ZM_W(13) ZM_W(14) ZM_W(15)
+        ZM_W(9) ZM_W(10) ZM_W(11) ZM_W(12) ZM_W(13) ZM_W(14) ZM_W(15) ZM_W(16)
+        ZM_W(17) ZM_W(18) ZM_W(19) ZM_W(20) ZM_W(21) ZM_W(22) ZM_W(23) ZM_W(24)
+        ZM_W(25) ZM_W(26) ZM_W(27) ZM_W(28) ZM_W(29) ZM_W(30) ZM_W(31)
 #undef ZM_W
     default: wait_vmcnt<0>(); break;
     }
@@ -267,7 +276,13 @@ struct Zm {
     static constexpr int NL = C::NLP + NLS_E;                         // copies per step per thread
     static constexpr int NSF = STORE ? 4 : 0, NSA = STORE ? 3 : 0;     // stores per output (flow, field)
     static constexpr int FZ = SUB == 0 ? 0 : C::SV * C::EPL;  // forcing z slot within an s-2 region
-    static_assert(NL + 2 * NSF <= 15, "the waits of a step cover at most 15 operations");
+    static_assert(NL + 2 * NSF <= 31, "the waits of a step cover at most 31 operations");
+    // copies a thread of the role issues per step
+    template <int ROLE>
+    __host__ __device__ static constexpr int nl()
+    {
+        return (C::ALLF && ROLE == 1) ? 0 : NL;
+    }
     // A field thread issues its copies of a step after its output stores (below) in the
     // FP32 kernels: with all waves issuing at once the last in line (the field waves)
     // fell about a quarter of the step behind (512^3 substep 2: 3.22 -> 2.66 ms; the
@@ -290,7 +305,7 @@ struct Zm {
     template <int ROLE>
     __host__ __device__ static constexpr int after(int k, int K)
     {
-        const int next = k + 1 < K ? NL : 0;
+        const int next = k + 1 < K ? nl<ROLE>() : 0;
         if (ROLE == 1 && LATE) return next + stores<1>(k - 1);
         return stores<ROLE>(k - 2) + next + stores<ROLE>(k - 1);
     }
@@ -302,14 +317,15 @@ struct Zm {
     {
         constexpr bool late = ROLE == 1 && LATE;
         for (int K = 1; K <= KMAX; K++) {
+            constexpr int n = nl<ROLE>();
             int end[64] = {}, issued = 0;  // end[p]: operations issued up to plane p's copies
-            end[0] = issued += NL;
-            if (K > 1) end[1] = issued += NL;
+            end[0] = issued += n;
+            if (K > 1) end[1] = issued += n;
             for (int k = 0; k < K; k++) {
                 if (issued - end[k] != after<ROLE>(k, K)) return false;
-                if (!late && k + 2 < K) end[k + 2] = issued += NL;
+                if (!late && k + 2 < K) end[k + 2] = issued += n;
                 issued += stores<ROLE>(k);
-                if (late && k + 2 < K) end[k + 2] = issued += NL;
+                if (late && k + 2 < K) end[k + 2] = issued += n;
             }
         }
         return true;
@@ -399,8 +415,8 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
     if (k >= K) return;
     zm_wait(Z::template after<ROLE>(k, K));
     // the copies of plane k + 2, into the slot plane k - 1 left (see Zm::LATE)
-    constexpr bool LATE = ROLE == 1 && Z::LATE;
-    if (!LATE && k + 2 < K) issue(k + 2, (J + 2) % 3);
+    constexpr bool LATE = ROLE == 1 && Z::LATE, ISSUES = !(C::ALLF && ROLE == 1);
+    if (ISSUES && !LATE && k + 2 < K) issue(k + 2, (J + 2) % 3);
     // this thread's planes (pb0 points 3 rows and 3 columns before its column in slot 0
     // of its role's region), s-2 values and exchange slots; the asm keeps the compiler
     // from hoisting addresses derived from them out of the step loop
@@ -583,7 +599,7 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
         }
     }
 
-    if (LATE && k + 2 < K) issue(k + 2, (J + 2) % 3);
+    if (ISSUES && LATE && k + 2 < K) issue(k + 2, (J + 2) % 3);
 
     // ---------------------------------------------------------------- fold in plane z'
     // The output plane's slots are free now: they start the accumulators of plane z' + 3.
@@ -753,14 +769,15 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
     const int cx = col % C::TX, cy = col / C::TX;
     const uint64_t plane_b = (uint64_t)nx * (uint64_t)ny * sizeof(T);
 
-    // Plane copies: wave-copy t = j * NW + wave (wave-uniform) brings 64 vectors of the
-    // flow planes (t < NIF) or of the field planes (t >= NIF); every lane's source is one
-    // field's row segment, the plane is added per step.
+    // Plane copies: wave-copy t = j * NWI + (issuing) wave (wave-uniform) brings 64 vectors
+    // of the flow planes (t < NIF) or of the field planes (t >= NIF); every lane's source
+    // is one field's row segment, the plane is added per step.
+    const int wi = wave & (C::NWI - 1), ti = tid & (C::NTI - 1);  // index among the issuing waves, threads
     const G<char> *pp[C::NLP];
     int pdst[C::NLP];  // destination offset within a slot's regions (values; wave-uniform)
 #pragma unroll
     for (int j = 0; j < C::NLP; j++) {
-        const int t = j * C::NW + wave;
+        const int t = j * C::NWI + wi;
         int f, v;
         if (t < C::NIF) {
             v = min(t * 64 + lane, 4 * C::PV - 1);
@@ -784,7 +801,7 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
     const G<T> *fz = fs + FHEAD + EPL * nx + EPL * ny;  // z phase table
 #pragma unroll
     for (int j = 0; j < Z::NLS_E; j++) {
-        int q = j * NT + tid;
+        int q = j * C::NTI + ti;
         spf[j] = SUB == 0 || q == C::SV;
         if (q >= C::SV) q = C::SV - 1;
         const int f = q / (NC / EPL), c = (q - f * (NC / EPL)) * EPL;
@@ -826,7 +843,7 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
         for (int j = 0; j < Z::NLS_E; j++) {
             const G<char> *src = spf[j] ? fzp : sp[j] + zob;
             __builtin_amdgcn_global_load_lds((gconst_void_t *)src,
-                                             (lds_void_t *)(lds + C::S2 + d * C::SREG + (j * NT + wave * 64) * EPL), 16,
+                                             (lds_void_t *)(lds + C::S2 + d * C::SREG + (j * C::NTI + wi * 64) * EPL), 16,
                                              0, 0);
         }
     };
@@ -845,8 +862,10 @@ k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int
             __builtin_amdgcn_global_load_lds((gconst_void_t *)p, (lds_void_t *)(lds + C::FH + h * 64 * EPL), 16, 0, 0);
         }
     }
-    issue(0, 0);
-    if (K > 1) issue(1, 1);
+    if (!C::ALLF || flow) {
+        issue(0, 0);
+        if (K > 1) issue(1, 1);
+    }
 
     // flow and field threads run separate copies of the step loop (the same waits and
     // barriers in the same order), so that each keeps only its own state in registers
