@@ -30,7 +30,7 @@
 
 namespace mhd {
 
-template <typename T, int TXV = 32>
+template <typename T, int TXV = 32, bool ALLFV = sizeof(T) == 8>
 struct ZmCfg {
     static constexpr int TX = TXV, TY = 8, NC = TX * TY;  // columns of a tile
     static constexpr int NT = 2 * NC;                      // flow + field threads
@@ -42,12 +42,14 @@ struct ZmCfg {
     // one step's planes: ln rho and u (read by flow threads) and A (field threads) land
     // in separate regions, whole wave-copies each
     static constexpr int NIF = (4 * PV + 63) / 64, NIA = (3 * PV + 63) / 64;
-    // FP64: the flow threads issue every copy of a step, the field threads none, so that
-    // the field waves (the longer path to the exchange barrier) start their output at
-    // once while the copies still leave at the top of the step (512^3 FP64: diagnostics
-    // substep 5.10 -> 4.98 ms, step 16.5 -> 16.3 ms; FP32 issues from every wave, the
-    // field waves after their stores, see Zm::LATE)
-    static constexpr bool ALLF = sizeof(T) == 8;
+    // ALLF (FP64, and the kernels with the diagnostics, see Zm::C): the flow threads
+    // issue every copy of a step, the field threads none, so that the field waves (the
+    // longer path to the exchange barrier) start their output at once while the copies
+    // still leave at the top of the step (512^3: FP64 diagnostics substep 5.10 -> 4.98
+    // ms, step 16.5 -> 16.3 ms; FP32 diagnostics substep 3.80 -> 3.46 ms).  FP32
+    // substeps 2 and 3 measured 5-9 % slower with it: there every wave issues, the
+    // field waves after their stores (Zm::LATE).
+    static constexpr bool ALLF = ALLFV;
     static constexpr int NWI = ALLF ? NW / 2 : NW, NTI = 64 * NWI;  // waves, threads that issue copies
     static constexpr int NLP = (NIF + NIA + NWI - 1) / NWI;  // plane copies per issuing thread per step
     static constexpr int FREG = NIF * 64 * EPL, AREG = NIA * 64 * EPL;  // values per slot
@@ -271,7 +273,7 @@ __device__ __forceinline__ void push3(T (&acc)[6], const T (&d)[3], const T (&w)
 
 template <typename T, int SUB, bool DIAG, bool STORE, bool UPW, int TXV>
 struct Zm {
-    using C = ZmCfg<T, TXV>;
+    using C = ZmCfg<T, TXV, sizeof(T) == 8 || DIAG>;
     static constexpr int NLS_E = STORE ? (SUB == 0 ? 1 : C::NLS) : 0;  // s-2 / forcing copies per step
     static constexpr int NL = C::NLP + NLS_E;                         // copies per step per thread
     static constexpr int NSF = STORE ? 4 : 0, NSA = STORE ? 3 : 0;     // stores per output (flow, field)
@@ -284,10 +286,10 @@ struct Zm {
         return (C::ALLF && ROLE == 1) ? 0 : NL;
     }
     // A field thread issues its copies of a step after its output stores (below) in the
-    // FP32 kernels: with all waves issuing at once the last in line (the field waves)
-    // fell about a quarter of the step behind (512^3 substep 2: 3.22 -> 2.66 ms; the
-    // diagnostics substep 1 % faster).  FP64 measured faster with the early issue.
-    static constexpr bool LATE = sizeof(T) == 4;
+    // FP32 kernels without ALLF: with all waves issuing at once the last in line (the
+    // field waves) fell about a quarter of the step behind (512^3 substep 2: 3.22 ->
+    // 2.66 ms).  FP64 measured faster with the early issue.
+    static constexpr bool LATE = sizeof(T) == 4 && !C::ALLF;
     // stores of a thread at step j (output plane j - 6; a flow thread with the deferred
     // exchange stores ln rho alone at its first output step and u of the previous plane
     // with every later one)
@@ -406,8 +408,8 @@ __device__ __forceinline__ void zm_body(int k, int K, T *lds, ZmState<T> &S, con
                                         uint32_t gcb, uint64_t plane_b, int zs, int out_set, T (&fa)[3], T (&fb)[3],
                                         bool &fon, ISSUE &issue)
 {
-    using C = ZmCfg<T, TXV>;
     using Z = Zm<T, SUB, DIAG, STORE, UPW, TXV>;
+    using C = typename Z::C;
     constexpr int NC = C::NC, PLE = C::PLE, XW = C::XW;
     constexpr int JD = J % 3;                       // delayed-set slot of plane z'
     constexpr int PO = PS<J, -3>::v;                // pending slot of the output plane (= J)
@@ -747,8 +749,8 @@ template <typename T, int SUB, bool DIAG, bool STORE, int WPE, bool UPW = false,
 __global__ void __launch_bounds__((ZmCfg<T, TXV>::NT), WPE)
 k_zm(const RunDesc<T> *__restrict__ runs, const TileEnt *__restrict__ tiles, int step)
 {
-    using C = ZmCfg<T, TXV>;
     using Z = Zm<T, SUB, DIAG, STORE, UPW, TXV>;
+    using C = typename Z::C;
     constexpr int NT = C::NT, NC = C::NC, EPL = C::EPL, XW = C::XW, PLE = C::PLE;
     static_assert(!(DIAG && SUB != 0), "diagnostics are taken in substep 0 only");
     __shared__ __align__(16) T lds[C::LDS];
